@@ -1,0 +1,216 @@
+/*
+ * fobf.h -- C ABI of the MI355X (gfx950) Fourier bilateral filter library.
+ *
+ * Method: "Optimized Fourier Bilateral Filtering", S. Ghosh, P. Nair,
+ * K. N. Chaudhury, IEEE Signal Processing Letters 25(10), 2018.
+ *
+ *   bilateral filter ............. eq. (1), Gaussian kernels eq. (2)
+ *   K-term cosine range kernel ... eq. (3), period 2T+1
+ *   kernel error / LS fit ........ eq. (4), (5)
+ *   period search, order search .. eq. (6), Algorithm 1
+ *
+ * Conventions shared by every entry point
+ *   - Images are single-channel float32, row-major; element (y, x) of an
+ *     image with leading dimension ld sits at ptr[y * ld + x].
+ *   - The spatial window is the square of radius r = ceil(3 * theta)
+ *     (the (6 theta + 1)^2 window of Sec. I) with separable taps
+ *     g(m) = exp(-m^2 / (2 theta^2)), g(0) = 1.
+ *   - Neighbours outside the image are left out of both sums of eq. (1)
+ *     (equivalently, every convolved channel is zero padded).
+ *   - The output is N / D literally: no clamping.  Where the cosine series
+ *     of eq. (3) dips below zero D can be <= 0 and the pixel is unreliable.
+ *   - Device pointers are caller-owned; the library never frees them.
+ *   - Non-OK statuses leave a message for fobf_last_error() (thread-local).
+ *   - fobf_fit and fobf_filter* are reentrant.  fobf_filter* only enqueue
+ *     work on the given HIP stream (NULL = the null stream) and never
+ *     synchronise; faults inside kernels surface at the caller's next sync.
+ */
+#ifndef FOBF_H
+#define FOBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FOBF_OK = 0,
+  FOBF_WARN_TOL = 1,   /* fit done, but its kernel error E exceeds eps      */
+  FOBF_EBUSY = 2,      /* serving: not finished yet / no capacity, retry    */
+  FOBF_EINVAL = -1,    /* invalid argument                                  */
+  FOBF_ENOMEM = -2,    /* allocation failed or request exceeds the budget   */
+  FOBF_EHIP = -3,      /* a HIP runtime call failed                         */
+  FOBF_EINTERNAL = -4, /* internal error                                    */
+  FOBF_ECANCELED = -5  /* serving: request cancelled or server stopped      */
+} fobf_status;
+
+typedef enum {
+  FOBF_FP32 = 0,        /* channels and intermediates stored in float32     */
+  FOBF_FP16_STAGE = 1,  /* channels/intermediates staged in fp16, fp32 acc  */
+  FOBF_BF16_STAGE = 2   /* channels/intermediates staged in bf16, fp32 acc  */
+} fobf_prec;
+
+typedef enum {
+  FOBF_ALGO_AUTO = 0,   /* library picks (tuned table, else heuristics)     */
+  FOBF_ALGO_VALU = 1,   /* vector-ALU separable convolution (fp32 only)     */
+  FOBF_ALGO_MFMA = 2    /* banded-Toeplitz matrix-core convolution          */
+} fobf_algo;
+
+#define FOBF_KMAX 32   /* largest order K (number of cosine terms)           */
+#define FOBF_RMAX 48   /* largest spatial radius ceil(3 theta), theta <= 16 */
+
+/* Result of a fit: the cosine series phi_hat(t) = sum_k c[k] cos(2 pi k t /
+ * (2T+1)) of eq. (3).  Plain value type. */
+typedef struct {
+  int R;                 /* intensity range: t runs over the integers -R..R */
+  int K;                 /* order (number of coefficients)                  */
+  int T;                 /* period parameter; the period is 2T+1            */
+  int Tmax;              /* upper end of the period scan used               */
+  double sigma;          /* range std-dev (0 for fobf_fit_samples)          */
+  double E;              /* kernel error E(K,T) of eq. (5) at the optimum   */
+  double delta;          /* max_t |phi(t) - phi_hat(t)| over t in -R..R     */
+  double c[FOBF_KMAX];   /* c[0..K-1]; entries >= K are zero                */
+} fobf_coef;
+
+/*
+ * fobf_fit -- least-squares coefficients and optimal period
+ *             (eq. (4)-(6), Algorithm 1).
+ *
+ * K >= 1 : fixed order.  Scans T = max(1, K-1) .. Tmax, solving eq. (5)
+ *          exactly for each T (float64 Householder QR of the system folded
+ *          onto t >= 0), and keeps the smallest E (smallest T on ties).
+ *          Returns FOBF_WARN_TOL when that E exceeds eps (out is valid).
+ * K == 0 : Algorithm 1: the smallest K <= FOBF_KMAX whose best period meets
+ *          E <= eps; FOBF_EINVAL if none does.
+ * Tmax <= 0 selects the default 4R.  Requires R >= 1, sigma > 0, eps > 0,
+ * 0 <= K <= min(FOBF_KMAX, R+1).  Results are cached per (R, sigma, K,
+ * eps, Tmax); thread-safe.
+ */
+fobf_status fobf_fit(int R, double sigma, int K, double eps, int Tmax,
+                     fobf_coef* out);
+
+/*
+ * fobf_fit_samples -- the same fit for an arbitrary even range kernel given
+ * by its samples b[t] = phi(t), t = 0..R (host array of R+1 doubles; the
+ * kernel must be even, phi(-t) = phi(t)).  The paper notes that the LS
+ * model applies to non-Gaussian kernels unchanged (Sec. I, contributions).
+ * K >= 1 only; not cached.  out->sigma is set to 0.
+ */
+fobf_status fobf_fit_samples(int R, const double* b, int K, double eps,
+                             int Tmax, fobf_coef* out);
+
+/*
+ * fobf_filter -- the K-term shiftable bilateral filter on one image.
+ *
+ * Computes, for every pixel i,
+ *   N(i) = sum_k c_k [cos(nu k f(i)) (w*(cos(nu k f) f))(i)
+ *                     + sin(nu k f(i)) (w*(sin(nu k f) f))(i)]
+ *   D(i) = the same with the factor f dropped inside the convolutions,
+ * nu = 2 pi / (2T+1), w = the truncated Gaussian spatial kernel, and
+ * writes out(i) = N(i) / D(i).  This equals eq. (1) with phi replaced by
+ * phi_hat of eq. (3) (Sec. II, first paragraph).
+ *
+ * d_in   device pointer, H x W floats with leading dimension ld_in.
+ * d_out  device pointer, H x W floats with leading dimension ld_out; must
+ *        not overlap d_in (tiles read their neighbours' halo).
+ * theta  spatial std-dev, 0 < theta, ceil(3 theta) <= FOBF_RMAX.
+ * K, T   order and period parameter, 1 <= K <= FOBF_KMAX, T >= 1.
+ * c      host array of K doubles (copied before return).
+ * prec   fobf_prec; algo fobf_algo (FOBF_ALGO_VALU supports FOBF_FP32 only).
+ * stream hipStream_t as void* (NULL = null stream).
+ * H, W >= 1, ld >= W.  H == 0 or W == 0 is a no-op returning FOBF_OK.
+ */
+fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W,
+                        int ld_in, int ld_out, double theta, int K, int T,
+                        const double* c, int prec, int algo,
+                        void* hip_stream);
+
+/* One image of a batch (all pointers device pointers, caller-owned). */
+typedef struct {
+  const float* d_in;
+  float* d_out;
+  int H, W, ld_in, ld_out;
+  double theta;
+  int K, T;
+  int prec;              /* fobf_prec                                       */
+  double c[FOBF_KMAX];
+} fobf_job;
+
+/*
+ * fobf_filter_batch -- filter n independent images of different sizes and
+ * parameters in ONE persistent launch: every workgroup pulls output tiles
+ * from a shared queue that spans all jobs (work stealing), so small and
+ * large images, and different radii and orders, share the machine.
+ *
+ * jobs      host array of n jobs (read before return).
+ * d_work    device workspace of at least fobf_batch_workspace_size(n)
+ *           bytes, caller-owned, not used by another call until this
+ *           call's work on the stream has finished.
+ * Same rules per job as fobf_filter.  n == 0 is a no-op.
+ */
+size_t fobf_batch_workspace_size(int n);
+fobf_status fobf_filter_batch(const fobf_job* jobs, int n, void* d_work,
+                              size_t work_bytes, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching.
+ *
+ * Requests (host images) may be submitted from any thread at any time.  A
+ * scheduler thread admits them while their device memory fits the HBM
+ * budget, fits (or looks up) their coefficients in a device-resident cache
+ * keyed by (R, sigma, K), copies them in on a copy stream and launches
+ * their tiles; requests that arrive while others run are admitted as
+ * memory frees up, and their work overlaps on the device.  Completion is
+ * reported by fobf_serve_poll.
+ * ---------------------------------------------------------------------- */
+typedef struct fobf_server fobf_server;
+
+typedef struct {
+  size_t hbm_budget_bytes;  /* device bytes for in-flight requests (>0)    */
+  int max_inflight;         /* requests in flight at once (>=1)            */
+  int max_batch;            /* requests merged into one launch (>=1)       */
+  int R;                    /* intensity range of the images (>=1)         */
+  double eps;               /* tolerance passed to fobf_fit (>0)           */
+} fobf_serve_cfg;
+
+typedef struct {
+  const float* h_in;        /* host image H x W, row-major, dense          */
+  float* h_out;             /* host output H x W; alive until polled done  */
+  int H, W;
+  double theta, sigma;
+  int K;                    /* order (>=1)                                 */
+  int prec;                 /* fobf_prec                                   */
+} fobf_request;
+
+typedef struct {
+  fobf_status status;       /* FOBF_EBUSY while pending                    */
+  double t_submit, t_admit, t_start, t_done;   /* seconds, monotonic clock */
+  int T;                    /* fitted period used                          */
+} fobf_result;
+
+fobf_status fobf_serve_create(const fobf_serve_cfg* cfg, fobf_server** out);
+fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req,
+                              uint64_t* ticket);
+/* wait != 0 blocks until the request is done.  Returns the request's final
+ * status (copied into *res too) or FOBF_EBUSY while it is pending. */
+fobf_status fobf_serve_poll(fobf_server* s, uint64_t ticket, int wait,
+                            fobf_result* res);
+fobf_status fobf_serve_destroy(fobf_server* s);
+
+/* Test hook: the next `count` device submissions of this server report a
+ * HIP error without launching anything (fault injection from the host). */
+fobf_status fobf_serve_inject_fault(fobf_server* s, int count);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char* fobf_last_error(void);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int fobf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOBF_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) Fourier bilateral filter: HIP kernels behind a C ABI
+(include/fobf.h) with a thin ctypes binding.  Importing the package loads
+libfobf.so and fails loudly if it has not been built."""
+from .fobf import (ALGO_AUTO, ALGO_MFMA, ALGO_VALU, BF16_STAGE, FP16_STAGE,
+                   FP32, KMAX, RMAX, Coef, FobfError, Server,
+                   batch_workspace_size, filter, filter_batch, fit,
+                   fit_samples, last_error, lib, make_job)
+
+__all__ = ["ALGO_AUTO", "ALGO_MFMA", "ALGO_VALU", "BF16_STAGE", "FP16_STAGE",
+           "FP32", "KMAX", "RMAX", "Coef", "FobfError", "Server",
+           "batch_workspace_size", "filter", "filter_batch", "fit",
+           "fit_samples", "last_error", "lib", "make_job"]

@@ -1,0 +1,108 @@
+// C ABI entry points: validation, parameter packing and dispatch.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "fobf_internal.h"
+
+namespace fobf {
+
+namespace {
+thread_local std::string t_error;
+}
+
+void set_error(const std::string& msg) { t_error = msg; }
+
+fobf_status fail(fobf_status st, const std::string& msg) {
+  t_error = msg;
+  return st;
+}
+
+static const char* error_cstr() { return t_error.c_str(); }
+
+int spatial_radius(double theta) {
+  if (!(theta > 0.0) || !std::isfinite(theta)) return -1;
+  const double r = std::ceil(3.0 * theta);
+  if (r > 1e6) return -1;
+  return static_cast<int>(r);
+}
+
+void make_params(ImageParams& p, const float* in, float* out, int H, int W,
+                 int ld_in, int ld_out, double theta, int K, int T,
+                 const double* c) {
+  std::memset(&p, 0, sizeof(p));
+  p.in = in;
+  p.out = out;
+  p.H = H;
+  p.W = W;
+  p.ld_in = ld_in;
+  p.ld_out = ld_out;
+  p.r = spatial_radius(theta);
+  p.K = K;
+  p.inv_period = static_cast<float>(1.0 / (2.0 * T + 1.0));
+  for (int k = 0; k < K; ++k) p.c[k] = static_cast<float>(c[k]);
+  const int r = p.r;
+  double acc = 0.0;
+  p.gsum[0] = 0.f;
+  for (int m = -r; m <= r; ++m) {
+    const double g = std::exp(-static_cast<double>(m) * m / (2.0 * theta * theta));
+    if (m >= 0) p.g[m] = static_cast<float>(g);
+    acc += g;
+    p.gsum[m + r + 1] = static_cast<float>(acc);
+  }
+}
+
+fobf_status validate_filter(const float* in, const float* out, int H, int W,
+                            int ld_in, int ld_out, double theta, int K, int T,
+                            const double* c, int prec, int algo) {
+  if (H < 0 || W < 0) return fail(FOBF_EINVAL, "fobf_filter: negative size");
+  if (H > 0 && W > 0) {
+    if (!in || !out) return fail(FOBF_EINVAL, "fobf_filter: NULL image pointer");
+    if (ld_in < W || ld_out < W)
+      return fail(FOBF_EINVAL, "fobf_filter: leading dimension below W");
+    const char* a0 = reinterpret_cast<const char*>(in);
+    const char* a1 = a0 + sizeof(float) * ((static_cast<size_t>(H) - 1) * ld_in + W);
+    const char* b0 = reinterpret_cast<const char*>(out);
+    const char* b1 = b0 + sizeof(float) * ((static_cast<size_t>(H) - 1) * ld_out + W);
+    if (a0 < b1 && b0 < a1)
+      return fail(FOBF_EINVAL, "fobf_filter: input and output overlap");
+  }
+  const int r = spatial_radius(theta);
+  if (r < 1) return fail(FOBF_EINVAL, "fobf_filter: theta must be positive and finite");
+  if (r > FOBF_RMAX) return fail(FOBF_EINVAL, "fobf_filter: ceil(3 theta) exceeds FOBF_RMAX");
+  if (K < 1 || K > FOBF_KMAX) return fail(FOBF_EINVAL, "fobf_filter: K out of range");
+  if (T < 1) return fail(FOBF_EINVAL, "fobf_filter: T must be >= 1");
+  if (!c) return fail(FOBF_EINVAL, "fobf_filter: c is NULL");
+  for (int k = 0; k < K; ++k)
+    if (!std::isfinite(c[k])) return fail(FOBF_EINVAL, "fobf_filter: non-finite coefficient");
+  if (prec < FOBF_FP32 || prec > FOBF_BF16_STAGE)
+    return fail(FOBF_EINVAL, "fobf_filter: unknown precision");
+  if (algo < FOBF_ALGO_AUTO || algo > FOBF_ALGO_MFMA)
+    return fail(FOBF_EINVAL, "fobf_filter: unknown algorithm");
+  if (algo == FOBF_ALGO_VALU && prec != FOBF_FP32)
+    return fail(FOBF_EINVAL, "fobf_filter: the vector path is float32 only");
+  return FOBF_OK;
+}
+
+}  // namespace fobf
+
+using namespace fobf;
+
+extern "C" fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W,
+                                   int ld_in, int ld_out, double theta, int K,
+                                   int T, const double* c, int prec, int algo,
+                                   void* hip_stream) {
+  fobf_status st = validate_filter(d_in, d_out, H, W, ld_in, ld_out, theta, K,
+                                   T, c, prec, algo);
+  if (st != FOBF_OK) return st;
+  if (H == 0 || W == 0) return FOBF_OK;
+  ImageParams p;
+  make_params(p, d_in, d_out, H, W, ld_in, ld_out, theta, K, T, c);
+  if (algo == FOBF_ALGO_AUTO) algo = auto_algo(p.r, K, prec);
+  if (algo == FOBF_ALGO_VALU) return launch_valu(p, hip_stream);
+  return launch_mfma(p, prec, hip_stream);
+}
+
+extern "C" const char* fobf_last_error(void) { return fobf::error_cstr(); }
+
+extern "C" int fobf_version(void) { return 100; }

@@ -1,0 +1,240 @@
+// Host-side float64 least-squares fit of the cosine range kernel.
+//
+// eq. (3): phi_hat(t) = sum_{k<K} c_k cos(nu k t), nu = 2 pi / (2T+1).
+// eq. (4): kernel error sum_{t=-R..R} (phi(t) - phi_hat(t))^2.
+// eq. (5): E(K,T) = min_c ||A c - b||^2 with A(t,k) = cos(nu k t), b(t) =
+//          phi(t), over the 2R+1 integers t of [-R, R].
+// eq. (6) and Algorithm 1: scan the period T, then (K = 0) raise K.
+//
+// Both phi and every column of A are even in t, so the 2R+1 equations fold
+// onto t = 0..R with weight 1 at t = 0 and 2 elsewhere; the weighted system
+// (rows scaled by sqrt(weight)) has the same minimiser and the same
+// residual norm.  It is solved with Householder QR in float64, because
+// A becomes badly conditioned for large T (normal equations are not used),
+// and E is evaluated from the explicit residual.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "fobf_internal.h"
+
+namespace fobf {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Solves min ||M c - y|| for an m x n column-major matrix M (m >= n) by
+// Householder QR.  M and y are overwritten.  Returns false when a column is
+// numerically dependent (pivot below tol * norm of the column).
+bool householder_lstsq(int m, int n, double* M, double* y, double* c) {
+  std::vector<double> colnorm(n);
+  for (int j = 0; j < n; ++j) {
+    double s = 0;
+    for (int i = 0; i < m; ++i) s += M[j * m + i] * M[j * m + i];
+    colnorm[j] = std::sqrt(s);
+  }
+  std::vector<double> diag(n);
+  for (int j = 0; j < n; ++j) {
+    double* a = M + j * m;
+    double s = 0;
+    for (int i = j; i < m; ++i) s += a[i] * a[i];
+    double alpha = std::sqrt(s);
+    if (alpha <= 1e-13 * colnorm[j] || alpha == 0.0) return false;
+    if (a[j] > 0) alpha = -alpha;
+    // v = a[j:] - alpha e_1, stored in place; H = I - 2 v v^T / (v^T v)
+    a[j] -= alpha;
+    double vtv = 0;
+    for (int i = j; i < m; ++i) vtv += a[i] * a[i];
+    diag[j] = alpha;
+    for (int k = j + 1; k < n; ++k) {
+      double* b = M + k * m;
+      double d = 0;
+      for (int i = j; i < m; ++i) d += a[i] * b[i];
+      d = 2.0 * d / vtv;
+      for (int i = j; i < m; ++i) b[i] -= d * a[i];
+    }
+    double d = 0;
+    for (int i = j; i < m; ++i) d += a[i] * y[i];
+    d = 2.0 * d / vtv;
+    for (int i = j; i < m; ++i) y[i] -= d * a[i];
+  }
+  // back substitution with the upper triangle (diag holds R_jj)
+  for (int j = n - 1; j >= 0; --j) {
+    double s = y[j];
+    for (int k = j + 1; k < n; ++k) s -= M[k * m + j] * c[k];
+    c[j] = s / diag[j];
+  }
+  return true;
+}
+
+// cos(2 pi * (k t mod P) / P): exact integer reduction of the argument.
+inline double cos_int(long kt, long P) {
+  return std::cos(kTwoPi * static_cast<double>(kt % P) / static_cast<double>(P));
+}
+
+struct FitOne {
+  bool ok;
+  double E;
+  double delta;
+  double c[FOBF_KMAX];
+};
+
+// E(K, T) of eq. (5) for samples b[0..R] of an even kernel.
+FitOne fit_one(int R, const double* b, int K, int T) {
+  FitOne r{};
+  const int m = R + 1;
+  const long P = 2L * T + 1;
+  std::vector<double> M(static_cast<size_t>(m) * K), y(m);
+  for (int t = 0; t <= R; ++t) {
+    const double w = (t == 0) ? 1.0 : std::sqrt(2.0);
+    for (int k = 0; k < K; ++k)
+      M[static_cast<size_t>(k) * m + t] = w * cos_int(static_cast<long>(k) * t, P);
+    y[t] = w * b[t];
+  }
+  r.ok = householder_lstsq(m, K, M.data(), y.data(), r.c);
+  if (!r.ok) return r;
+  // explicit residual of the unfolded system: t = 0 once, t > 0 twice
+  double E = 0, dmax = 0;
+  for (int t = 0; t <= R; ++t) {
+    double s = 0;
+    for (int k = 0; k < K; ++k) s += r.c[k] * cos_int(static_cast<long>(k) * t, P);
+    const double d = s - b[t];
+    E += (t == 0 ? 1.0 : 2.0) * d * d;
+    dmax = std::max(dmax, std::fabs(d));
+  }
+  r.E = E;
+  r.delta = dmax;
+  return r;
+}
+
+// Best period for fixed K: T = max(1, K-1) .. Tmax, smallest E, first T on
+// exact ties.  (For T <= K-2 the columns k and 2T+1-k coincide, so those
+// periods are rank deficient and skipped.)
+bool scan_T(int R, const double* b, int K, int Tmax, int* Tbest, FitOne* best) {
+  bool found = false;
+  for (int T = std::max(1, K - 1); T <= Tmax; ++T) {
+    FitOne f = fit_one(R, b, K, T);
+    if (!f.ok) continue;
+    if (!found || f.E < best->E) {
+      *best = f;
+      *Tbest = T;
+      found = true;
+    }
+  }
+  return found;
+}
+
+std::vector<double> gaussian_samples(int R, double sigma) {
+  std::vector<double> b(R + 1);
+  for (int t = 0; t <= R; ++t) b[t] = std::exp(-(double)t * t / (2.0 * sigma * sigma));
+  return b;
+}
+
+void fill(fobf_coef* out, int R, int K, int T, int Tmax, double sigma,
+          const FitOne& f) {
+  std::memset(out, 0, sizeof(*out));
+  out->R = R;
+  out->K = K;
+  out->T = T;
+  out->Tmax = Tmax;
+  out->sigma = sigma;
+  out->E = f.E;
+  out->delta = f.delta;
+  for (int k = 0; k < K; ++k) out->c[k] = f.c[k];
+}
+
+std::mutex g_cache_mu;
+std::map<std::tuple<int, uint64_t, int, uint64_t, int>, fobf_coef> g_cache;
+
+uint64_t bits(double d) {
+  uint64_t u;
+  std::memcpy(&u, &d, sizeof(u));
+  return u;
+}
+
+fobf_status fit_samples_impl(int R, const double* b, int K, double eps,
+                             int Tmax, double sigma, fobf_coef* out) {
+  if (K >= 1) {
+    int T = 0;
+    FitOne f{};
+    if (!scan_T(R, b, K, Tmax, &T, &f))
+      return fail(FOBF_EINTERNAL, "fobf_fit: no full-rank period found");
+    fill(out, R, K, T, Tmax, sigma, f);
+    if (!(f.E <= eps)) {
+      set_error("fobf_fit: E(K,T*) exceeds eps");
+      return FOBF_WARN_TOL;
+    }
+    return FOBF_OK;
+  }
+  // Algorithm 1: smallest K whose best period reaches E <= eps.
+  const int Klim = std::min(FOBF_KMAX, R + 1);
+  for (int k = 1; k <= Klim; ++k) {
+    int T = 0;
+    FitOne f{};
+    if (!scan_T(R, b, k, Tmax, &T, &f)) continue;
+    if (f.E <= eps) {
+      fill(out, R, k, T, Tmax, sigma, f);
+      return FOBF_OK;
+    }
+  }
+  return fail(FOBF_EINVAL, "fobf_fit: no order up to FOBF_KMAX meets eps");
+}
+
+}  // namespace
+}  // namespace fobf
+
+using namespace fobf;
+
+extern "C" fobf_status fobf_fit(int R, double sigma, int K, double eps,
+                                int Tmax, fobf_coef* out) {
+  if (!out) return fail(FOBF_EINVAL, "fobf_fit: out is NULL");
+  if (R < 1) return fail(FOBF_EINVAL, "fobf_fit: R must be >= 1");
+  if (!(sigma > 0.0) || !std::isfinite(sigma))
+    return fail(FOBF_EINVAL, "fobf_fit: sigma must be positive and finite");
+  if (!(eps > 0.0)) return fail(FOBF_EINVAL, "fobf_fit: eps must be > 0");
+  if (K < 0 || K > FOBF_KMAX || K > R + 1)
+    return fail(FOBF_EINVAL, "fobf_fit: K out of range");
+  if (Tmax <= 0) Tmax = 4 * R;
+  if (Tmax < std::max(1, K - 1))
+    return fail(FOBF_EINVAL, "fobf_fit: Tmax below K-1");
+  auto key = std::make_tuple(R, bits(sigma), K, bits(eps), Tmax);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      *out = it->second;
+      if (!(out->E <= eps)) {
+        set_error("fobf_fit: E(K,T*) exceeds eps");
+        return FOBF_WARN_TOL;
+      }
+      return FOBF_OK;
+    }
+  }
+  std::vector<double> b = gaussian_samples(R, sigma);
+  fobf_status st = fit_samples_impl(R, b.data(), K, eps, Tmax, sigma, out);
+  if (st == FOBF_OK || st == FOBF_WARN_TOL) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache[key] = *out;
+  }
+  return st;
+}
+
+extern "C" fobf_status fobf_fit_samples(int R, const double* b, int K,
+                                        double eps, int Tmax, fobf_coef* out) {
+  if (!out || !b) return fail(FOBF_EINVAL, "fobf_fit_samples: NULL pointer");
+  if (R < 1) return fail(FOBF_EINVAL, "fobf_fit_samples: R must be >= 1");
+  if (!(eps > 0.0)) return fail(FOBF_EINVAL, "fobf_fit_samples: eps must be > 0");
+  if (K < 1 || K > FOBF_KMAX || K > R + 1)
+    return fail(FOBF_EINVAL, "fobf_fit_samples: K out of range");
+  for (int t = 0; t <= R; ++t)
+    if (!std::isfinite(b[t]))
+      return fail(FOBF_EINVAL, "fobf_fit_samples: non-finite sample");
+  if (Tmax <= 0) Tmax = 4 * R;
+  if (Tmax < std::max(1, K - 1))
+    return fail(FOBF_EINVAL, "fobf_fit_samples: Tmax below K-1");
+  return fit_samples_impl(R, b, K, eps, Tmax, 0.0, out);
+}

@@ -1,0 +1,53 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/fobf.h"
+
+namespace fobf {
+
+// Thread-local error message behind fobf_last_error().
+void set_error(const std::string& msg);
+fobf_status fail(fobf_status st, const std::string& msg);
+
+// Spatial radius ceil(3 theta) computed in double (the oracle does the
+// same), or -1 when theta is not positive and finite.
+int spatial_radius(double theta);
+
+// Kernel-side parameter block of one image: passed by value to the
+// single-image kernels and stored in a device table for batched launches.
+struct ImageParams {
+  const float* in;
+  float* out;
+  int H, W, ld_in, ld_out;
+  int r;             // spatial radius
+  int K;             // order
+  float inv_period;  // 1 / (2T + 1)
+  int pad_;
+  float c[FOBF_KMAX];       // c_k in float32
+  float g[FOBF_RMAX + 1];   // taps g(0..r); g(-m) = g(m)
+  float gsum[2 * FOBF_RMAX + 2];  // gsum[j] = sum_{m=-r}^{j-r-1} g(m), j=0..2r+1
+};
+
+// Fill an ImageParams from API arguments (validated by the caller).
+void make_params(ImageParams& p, const float* in, float* out, int H, int W,
+                 int ld_in, int ld_out, double theta, int K, int T,
+                 const double* c);
+
+// Validate fobf_filter arguments; returns FOBF_OK or an error with message.
+fobf_status validate_filter(const float* in, const float* out, int H, int W,
+                            int ld_in, int ld_out, double theta, int K, int T,
+                            const double* c, int prec, int algo);
+
+// Launchers (fobf_valu.hip / fobf_mfma.hip).  Return FOBF_EHIP on launch
+// failure with the message set.
+fobf_status launch_valu(const ImageParams& p, void* stream);
+fobf_status launch_mfma(const ImageParams& p, int prec, void* stream);
+
+// Choice made by FOBF_ALGO_AUTO.
+int auto_algo(int r, int K, int prec);
+
+}  // namespace fobf

@@ -1,0 +1,312 @@
+"""Thin ctypes binding of libfobf.so (argument marshalling only).
+
+Every computation runs inside the library: the float64 fit on the host,
+the filter in HIP kernels on the GPU.  torch is used for device memory and
+streams only.  There is no fallback: if the library is missing, importing
+this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfobf.so")
+
+KMAX = 32
+RMAX = 48
+
+FP32, FP16_STAGE, BF16_STAGE = 0, 1, 2
+ALGO_AUTO, ALGO_VALU, ALGO_MFMA = 0, 1, 2
+
+OK, WARN_TOL, EBUSY = 0, 1, 2
+EINVAL, ENOMEM, EHIP, EINTERNAL, ECANCELED = -1, -2, -3, -4, -5
+
+_PREC = {"fp32": FP32, "f32": FP32, "fp16": FP16_STAGE, "f16": FP16_STAGE,
+         "bf16": BF16_STAGE}
+_ALGO = {"auto": ALGO_AUTO, "valu": ALGO_VALU, "mfma": ALGO_MFMA}
+
+EXPORTS = [
+    "fobf_fit", "fobf_fit_samples", "fobf_filter", "fobf_batch_workspace_size",
+    "fobf_filter_batch", "fobf_serve_create", "fobf_serve_submit",
+    "fobf_serve_poll", "fobf_serve_destroy", "fobf_serve_inject_fault",
+    "fobf_last_error", "fobf_version",
+]
+
+
+class FobfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class _Coef(C.Structure):
+    _fields_ = [("R", C.c_int), ("K", C.c_int), ("T", C.c_int),
+                ("Tmax", C.c_int), ("sigma", C.c_double), ("E", C.c_double),
+                ("delta", C.c_double), ("c", C.c_double * KMAX)]
+
+
+class _Job(C.Structure):
+    _fields_ = [("d_in", C.c_void_p), ("d_out", C.c_void_p), ("H", C.c_int),
+                ("W", C.c_int), ("ld_in", C.c_int), ("ld_out", C.c_int),
+                ("theta", C.c_double), ("K", C.c_int), ("T", C.c_int),
+                ("prec", C.c_int), ("c", C.c_double * KMAX)]
+
+
+class _ServeCfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_inflight", C.c_int),
+                ("max_batch", C.c_int), ("R", C.c_int), ("eps", C.c_double)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("h_in", C.c_void_p), ("h_out", C.c_void_p), ("H", C.c_int),
+                ("W", C.c_int), ("theta", C.c_double), ("sigma", C.c_double),
+                ("K", C.c_int), ("prec", C.c_int)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double), ("T", C.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -m paper_1811_02168_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(LIB_PATH)
+    lib.fobf_fit.argtypes = [C.c_int, C.c_double, C.c_int, C.c_double, C.c_int,
+                             C.POINTER(_Coef)]
+    lib.fobf_fit_samples.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int,
+                                     C.c_double, C.c_int, C.POINTER(_Coef)]
+    lib.fobf_filter.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                C.POINTER(C.c_double), C.c_int, C.c_int,
+                                C.c_void_p]
+    def bind(name, argtypes, restype=C.c_int):
+        if hasattr(lib, name):
+            fn = getattr(lib, name)
+            fn.argtypes = argtypes
+            fn.restype = restype
+
+    bind("fobf_batch_workspace_size", [C.c_int], C.c_size_t)
+    bind("fobf_filter_batch", [C.POINTER(_Job), C.c_int, C.c_void_p,
+                               C.c_size_t, C.c_void_p])
+    bind("fobf_serve_create", [C.POINTER(_ServeCfg), C.POINTER(C.c_void_p)])
+    bind("fobf_serve_submit", [C.c_void_p, C.POINTER(_Request),
+                               C.POINTER(C.c_uint64)])
+    bind("fobf_serve_poll", [C.c_void_p, C.c_uint64, C.c_int,
+                             C.POINTER(_Result)])
+    bind("fobf_serve_destroy", [C.c_void_p])
+    bind("fobf_serve_inject_fault", [C.c_void_p, C.c_int])
+    lib.fobf_last_error.restype = C.c_char_p
+    lib.fobf_fit.restype = C.c_int
+    lib.fobf_fit_samples.restype = C.c_int
+    lib.fobf_filter.restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    m = lib.fobf_last_error()
+    return m.decode() if m else ""
+
+
+def _check(st, allow=(OK,)):
+    if st in allow:
+        return st
+    raise FobfError(st, last_error())
+
+
+def _prec(p):
+    return _PREC[p] if isinstance(p, str) else int(p)
+
+
+def _algo(a):
+    return _ALGO[a] if isinstance(a, str) else int(a)
+
+
+def _carr(c, K):
+    c = np.asarray(c, dtype=np.float64).ravel()
+    if len(c) < K:
+        raise ValueError("need K coefficients")
+    arr = (C.c_double * KMAX)()
+    for k in range(K):
+        arr[k] = float(c[k])
+    return arr
+
+
+@dataclass
+class Coef:
+    """Fitted cosine range kernel of eq. (3): K, T and c[0..K-1]."""
+    R: int
+    K: int
+    T: int
+    Tmax: int
+    sigma: float
+    E: float
+    delta: float
+    c: np.ndarray = field(repr=False)
+    status: int = OK
+
+    @staticmethod
+    def _from(s: _Coef, status: int) -> "Coef":
+        return Coef(s.R, s.K, s.T, s.Tmax, s.sigma, s.E, s.delta,
+                    np.array(s.c[:s.K], dtype=np.float64), status)
+
+
+def fit(R: int, sigma: float, K: int, eps: float = 0.1, Tmax: int = 0) -> Coef:
+    """fobf_fit: K >= 1 fixed order (T scan), K == 0 Algorithm 1."""
+    out = _Coef()
+    st = lib.fobf_fit(int(R), float(sigma), int(K), float(eps), int(Tmax),
+                      C.byref(out))
+    _check(st, (OK, WARN_TOL))
+    return Coef._from(out, st)
+
+
+def fit_samples(R: int, b, K: int, eps: float = 0.1, Tmax: int = 0) -> Coef:
+    """fobf_fit_samples: arbitrary even kernel from samples b[0..R]."""
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    if b.shape != (R + 1,):
+        raise ValueError("b must hold R+1 samples")
+    out = _Coef()
+    st = lib.fobf_fit_samples(int(R), b.ctypes.data_as(C.POINTER(C.c_double)),
+                              int(K), float(eps), int(Tmax), C.byref(out))
+    _check(st, (OK, WARN_TOL))
+    return Coef._from(out, st)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def _check_image(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float32 or t.dim() != 2 or t.stride(1) != 1:
+        raise TypeError(f"{name} must be 2-D float32 with unit column stride")
+
+
+def filter(img, theta: float, K: int, T: int, c, prec="fp32", algo="auto",
+           out=None, stream=None):
+    """fobf_filter on a 2-D float32 CUDA tensor; returns the output tensor.
+    Enqueued on ``stream`` (default: torch's current stream)."""
+    import torch
+    _check_image(img, "img")
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=img.device)
+    _check_image(out, "out")
+    if tuple(out.shape) != (H, W):
+        raise ValueError("out shape mismatch")
+    carr = _carr(c, K)
+    st = lib.fobf_filter(C.c_void_p(img.data_ptr()), C.c_void_p(out.data_ptr()),
+                         H, W, img.stride(0), out.stride(0), float(theta),
+                         int(K), int(T), carr, _prec(prec), _algo(algo),
+                         _stream_ptr(stream))
+    _check(st)
+    return out
+
+
+def batch_workspace_size(n: int) -> int:
+    return int(lib.fobf_batch_workspace_size(int(n)))
+
+
+def make_job(img, out, theta, K, T, c, prec="fp32") -> _Job:
+    _check_image(img, "img")
+    _check_image(out, "out")
+    j = _Job()
+    j.d_in = img.data_ptr()
+    j.d_out = out.data_ptr()
+    j.H, j.W = img.shape
+    j.ld_in = img.stride(0)
+    j.ld_out = out.stride(0)
+    j.theta = float(theta)
+    j.K = int(K)
+    j.T = int(T)
+    j.prec = _prec(prec)
+    j.c = _carr(c, K)
+    return j
+
+
+def filter_batch(jobs, workspace=None, stream=None):
+    """fobf_filter_batch over a list of _Job (see make_job): one persistent
+    launch.  ``workspace`` is a uint8 CUDA tensor of at least
+    batch_workspace_size(len(jobs)) bytes (allocated if None)."""
+    import torch
+    n = len(jobs)
+    arr = (_Job * max(1, n))(*jobs)
+    need = batch_workspace_size(n)
+    if workspace is None:
+        dev = torch.device("cuda")
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    st = lib.fobf_filter_batch(arr, n, C.c_void_p(workspace.data_ptr()),
+                               workspace.numel(), _stream_ptr(stream))
+    _check(st)
+    return workspace
+
+
+class Server:
+    """Continuous-batching server (fobf_serve_*) over host images."""
+
+    def __init__(self, hbm_budget_bytes=32 << 30, max_inflight=64,
+                 max_batch=16, R=255, eps=0.1):
+        cfg = _ServeCfg(int(hbm_budget_bytes), int(max_inflight),
+                        int(max_batch), int(R), float(eps))
+        h = C.c_void_p()
+        _check(lib.fobf_serve_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, img: np.ndarray, out: np.ndarray, theta, sigma, K,
+               prec="fp32") -> int:
+        if img.dtype != np.float32 or not img.flags.c_contiguous or img.ndim != 2:
+            raise TypeError("img must be a C-contiguous 2-D float32 array")
+        if out.dtype != np.float32 or not out.flags.c_contiguous or out.shape != img.shape:
+            raise TypeError("out must match img (C-contiguous float32)")
+        req = _Request(img.ctypes.data, out.ctypes.data, img.shape[0],
+                       img.shape[1], float(theta), float(sigma), int(K),
+                       _prec(prec))
+        t = C.c_uint64()
+        _check(lib.fobf_serve_submit(self._h, C.byref(req), C.byref(t)))
+        self._keep[t.value] = (img, out)
+        return t.value
+
+    def poll(self, ticket: int, wait=True):
+        res = _Result()
+        st = lib.fobf_serve_poll(self._h, C.c_uint64(ticket), int(bool(wait)),
+                                 C.byref(res))
+        if st != EBUSY:
+            self._keep.pop(ticket, None)
+        return st, res
+
+    def inject_fault(self, count=1):
+        _check(lib.fobf_serve_inject_fault(self._h, int(count)))
+
+    def close(self):
+        if self._h:
+            _check(lib.fobf_serve_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,179 @@
+"""GPU parity: the HIP filter (through the C ABI) against the FP64 oracle's
+Fourier filter with the same (K, T, c), element by element.
+
+Tolerance: 0.5 intensity levels max-abs on pixels whose oracle denominator
+satisfies D(i)/W(i) >= 0.01 (where the cosine series keeps the
+denominator away from zero; D/W is the normalised denominator, 1 for the
+exact Gaussian kernel at a flat region).  Masked pixels are counted and
+reported.  FP32 results are additionally held to 0.05 levels, the bound
+derived in the design doc from float32 rounding of 29 channels x 61-tap sums.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 0.5          # intensity levels, FP32 contract
+TOL_F32 = 0.05     # derived float32 bound
+DMASK = 0.01
+
+
+def gpu_filter(f, theta, K, T, c, prec="fp32", algo="auto", pad=0):
+    import torch
+    import paper_1811_02168_amd as F
+    H, W = f.shape
+    dev = torch.device("cuda")
+    buf = torch.zeros((H, W + pad), dtype=torch.float32, device=dev)
+    buf[:, :W] = torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32))
+    img = buf[:, :W]
+    obuf = torch.full((H, W + pad + 3), -777.0, dtype=torch.float32, device=dev)
+    out = obuf[:, :W]
+    F.filter(img, theta, K, T, c, prec=prec, algo=algo, out=out)
+    torch.cuda.synchronize()
+    o = obuf.cpu().numpy()
+    if pad + 3 > 0:
+        assert np.all(o[:, W:] == -777.0), "write outside the output view"
+    return o[:, :W].astype(np.float64)
+
+
+def compare(f, theta, K, T, c, got):
+    ref, num, den = O.fourier_direct(f, theta, K, T, c, return_nd=True)
+    Wi = O.blur_weight(*f.shape, theta)
+    mask = den / Wi >= DMASK
+    err = np.abs(got - ref)
+    e_masked = float(err[mask].max()) if mask.any() else 0.0
+    return {"maxabs": e_masked,
+            "maxabs_all": float(np.nan_to_num(err, nan=np.inf).max()),
+            "masked": int((~mask).sum()),
+            "psnr": O.psnr(ref[mask], got[mask]) if mask.any() else math.inf}
+
+
+def fitted(sigma, K):
+    r = O.fit(255, sigma, K)
+    return r["T"], r["c"]
+
+
+ALGOS = ["valu", "mfma"]
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_c1_full(algo):
+    cfg = workloads.C1
+    f = cfg.image()
+    T, c = fitted(cfg.sigmas[0], cfg.K)
+    got = gpu_filter(f, cfg.theta, cfg.K, T, c, algo=algo)
+    s = compare(f, cfg.theta, cfg.K, T, c, got)
+    print("C1", algo, s)
+    assert s["maxabs"] <= TOL_F32
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("sigma", workloads.C2.sigmas)
+def test_c2_crop(algo, sigma):
+    cfg = workloads.C2
+    f = cfg.image()[100:400, 200:637]          # 300 x 437, ragged tiles
+    T, c = fitted(sigma, cfg.K)
+    got = gpu_filter(f, cfg.theta, cfg.K, T, c, algo=algo)
+    s = compare(f, cfg.theta, cfg.K, T, c, got)
+    print("C2", algo, sigma, T, s)
+    assert s["maxabs"] <= TOL_F32
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("sigma", workloads.C3.sigmas)
+def test_c3_crop(algo, sigma):
+    cfg = workloads.C3
+    f = cfg.image()[1000:1321, 3000:3283]      # 321 x 283
+    T, c = fitted(sigma, cfg.K)
+    got = gpu_filter(f, cfg.theta, cfg.K, T, c, algo=algo)
+    s = compare(f, cfg.theta, cfg.K, T, c, got)
+    print("C3crop", algo, sigma, T, s)
+    assert s["maxabs"] <= TOL_F32
+
+
+EDGE = [
+    # (H, W, theta, K, sigma)
+    (1, 1, 2.0, 4, 30.0),
+    (1, 37, 1.5, 3, 20.0),
+    (53, 1, 2.5, 5, 40.0),
+    (7, 5, 4.0, 6, 30.0),        # image smaller than the radius
+    (97, 131, 2.3, 4, 25.0),     # primes, non-integer theta
+    (64, 64, 3.0, 1, 30.0),      # K = 1: plain Gaussian blur
+    (70, 90, 1.0, 2, 60.0),      # r = 3
+    (40, 200, 5.0, 16, 12.0),    # large K
+    (150, 120, 16.0, 3, 80.0),   # r = 48, the largest radius
+    (33, 65, 0.2, 4, 30.0),      # r = 1
+]
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("H,W,theta,K,sigma", EDGE)
+def test_edge_cases(algo, H, W, theta, K, sigma):
+    f = workloads.voronoi_image(H, W, max(2, (H * W) // 400), True, H * 1000 + W)
+    T, c = fitted(sigma, K)
+    got = gpu_filter(f, theta, K, T, c, algo=algo, pad=5)
+    s = compare(f, theta, K, T, c, got)
+    print("edge", algo, H, W, theta, K, T, s)
+    assert s["maxabs"] <= TOL_F32
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_non_integer_image_and_random_coefficients(algo):
+    """The library accepts any real f and any c (D may change sign)."""
+    rng = np.random.default_rng(9)
+    f = rng.uniform(0, 255, size=(61, 77))
+    c = np.array([0.5, 0.3, 0.15, 0.05])
+    got = gpu_filter(f, 1.8, 4, 90, c, algo=algo)
+    s = compare(f, 1.8, 4, 90, c, got)
+    assert s["maxabs"] <= TOL_F32
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_deterministic(algo):
+    f = workloads.C2.image()[:200, :300]
+    T, c = fitted(30.0, 6)
+    a = gpu_filter(f, 5.0, 6, T, c, algo=algo)
+    b = gpu_filter(f, 5.0, 6, T, c, algo=algo)
+    assert np.array_equal(a, b)
+
+
+def test_constant_image_fixed_point():
+    f = np.full((77, 91), 143.0)
+    for algo in ALGOS:
+        T, c = fitted(30.0, 6)
+        got = gpu_filter(f, 4.0, 6, T, c, algo=algo)
+        assert np.max(np.abs(got - 143.0)) < 1e-3
+
+
+def sample_points(H, W, n, seed):
+    rng = np.random.default_rng(seed)
+    ys = list(rng.integers(0, H, n))
+    xs = list(rng.integers(0, W, n))
+    for y in (0, 1, 29, 30, 31, H // 2, H - 31, H - 2, H - 1):
+        for x in (0, 1, 30, 63, 64, W // 2, W - 31, W - 1):
+            ys.append(y)
+            xs.append(x)
+    return np.array(ys), np.array(xs)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_c3_full_size_sampled(algo):
+    """4096^2, theta=10, K=8 (the benchmark launch): sampled outputs against
+    eq. (1) evaluated pixel by pixel with the fitted cosine series."""
+    cfg = workloads.C3
+    f = cfg.image()
+    for sigma in cfg.sigmas:
+        T, c = fitted(sigma, cfg.K)
+        got = gpu_filter(f, cfg.theta, cfg.K, T, c, algo=algo)
+        ys, xs = sample_points(*f.shape, 600, int(sigma))
+        ref, num, den = O.brute_bf_points(f, cfg.theta, O.cosine_series(c, T),
+                                          ys, xs)
+        err = np.abs(got[ys, xs] - ref)
+        print("C3 full", algo, sigma, T, float(err.max()))
+        assert float(err.max()) <= TOL_F32
+        assert np.all(np.isfinite(got))

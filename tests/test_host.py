@@ -1,0 +1,139 @@
+"""CPU-side tests of the C ABI: the library loads and exports what the header
+declares, the float64 host fit matches the oracle's fit, and argument
+validation rejects bad calls before any device work."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "fobf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fobf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_header_symbols():
+    import ctypes
+    import paper_1811_02168_amd as F
+    names = header_functions()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(F.lib, n)]
+    assert not missing, missing
+    # nm agrees: every symbol is a global text symbol
+    lib = ctypes.CDLL(F.fobf.LIB_PATH)
+    for n in names:
+        assert getattr(lib, n) is not None
+    assert F.lib.fobf_version() >= 100
+
+
+SIGMAS = [10.0, 20.0, 30.0, 50.0, 80.0, 100.0]
+
+
+@pytest.mark.parametrize("sigma", SIGMAS)
+def test_host_fit_matches_oracle(sigma):
+    import paper_1811_02168_amd as F
+    for K in (1, 2, 3, 4, 6, 8, 10):
+        ref = O.fit(255, sigma, K)
+        got = F.fit(255, sigma, K, eps=1e9)
+        assert got.K == K and got.R == 255 and got.Tmax == 1020
+        if ref["E"] > 1e-12:
+            assert got.T == ref["T"], (sigma, K)
+            np.testing.assert_allclose(got.c, ref["c"], rtol=1e-9, atol=1e-12)
+            assert got.E == pytest.approx(ref["E"], rel=1e-8)
+        else:
+            # at the float64 noise floor several periods are optimal
+            assert got.E <= 1e-12
+            E_at = O.fit_E(255, sigma, K, got.T)[1]
+            assert E_at <= 1e-12
+        assert got.delta == pytest.approx(
+            O.kernel_maxdev(255, sigma, got.c, got.T), rel=1e-6, abs=1e-14)
+
+
+def test_host_fit_fig1_and_warn():
+    import paper_1811_02168_amd as F
+    c = F.fit(255, 50.0, 4, eps=0.1)
+    assert c.T == 203 and c.status == F.fobf.OK
+    c1 = F.fit(255, 30.0, 4, eps=0.1)     # E = 0.21 > eps: warn, still valid
+    assert c1.status == F.fobf.WARN_TOL and c1.E > 0.1
+
+
+@pytest.mark.parametrize("sigma,eps", [(50.0, 0.1), (30.0, 0.1), (15.0, 0.1),
+                                       (30.0, 1e-3), (50.0, 1e-5)])
+def test_host_algorithm1_matches_oracle(sigma, eps):
+    import paper_1811_02168_amd as F
+    ref = O.algorithm1(255, sigma, eps)
+    got = F.fit(255, sigma, 0, eps=eps)
+    assert got.K == ref["K"]
+    assert got.T == ref["T"]
+    np.testing.assert_allclose(got.c, ref["c"], rtol=1e-8, atol=1e-12)
+
+
+def test_host_fit_samples_nongaussian():
+    import paper_1811_02168_amd as F
+    R = 255
+    t = np.arange(R + 1, dtype=np.float64)
+    b = 1.0 / (1.0 + (t / 25.0) ** 2)          # Lorentzian range kernel
+    got = F.fit_samples(R, b, 6, eps=1e9)
+    ref = O.fit(R, lambda tt: 1.0 / (1.0 + (tt / 25.0) ** 2), 6)
+    assert got.T == ref["T"]
+    np.testing.assert_allclose(got.c, ref["c"], rtol=1e-9, atol=1e-12)
+    assert got.sigma == 0.0
+
+
+def test_fit_invalid_arguments():
+    import paper_1811_02168_amd as F
+    for args in [(0, 30.0, 4), (255, -1.0, 4), (255, 30.0, 33),
+                 (255, float("nan"), 4), (3, 30.0, 5)]:
+        with pytest.raises(F.FobfError) as e:
+            F.fit(*args)
+        assert e.value.status == F.fobf.EINVAL
+    with pytest.raises(F.FobfError):
+        F.fit(255, 30.0, 4, eps=0.0)
+
+
+def test_filter_validation_without_device():
+    """Invalid arguments are rejected on the host, before any HIP call."""
+    import ctypes as C
+    import paper_1811_02168_amd as F
+    lib = F.lib
+    c = (C.c_double * 32)(*([1.0] + [0.0] * 31))
+    fake_in, fake_out = C.c_void_p(0x10000), C.c_void_p(0x20000000)
+    cases = [
+        (None, fake_out, 4, 4, 4, 4, 1.0, 2, 5, c, 0, 0),       # null input
+        (fake_in, fake_out, 4, 4, 3, 4, 1.0, 2, 5, c, 0, 0),    # ld < W
+        (fake_in, fake_out, 4, 4, 4, 4, 0.0, 2, 5, c, 0, 0),    # theta 0
+        (fake_in, fake_out, 4, 4, 4, 4, 17.0, 2, 5, c, 0, 0),   # r > RMAX
+        (fake_in, fake_out, 4, 4, 4, 4, 1.0, 0, 5, c, 0, 0),    # K = 0
+        (fake_in, fake_out, 4, 4, 4, 4, 1.0, 33, 5, c, 0, 0),   # K > KMAX
+        (fake_in, fake_out, 4, 4, 4, 4, 1.0, 2, 0, c, 0, 0),    # T = 0
+        (fake_in, fake_out, 4, 4, 4, 4, 1.0, 2, 5, None, 0, 0),  # c null
+        (fake_in, fake_out, 4, 4, 4, 4, 1.0, 2, 5, c, 7, 0),    # prec
+        (fake_in, fake_out, 4, 4, 4, 4, 1.0, 2, 5, c, 0, 9),    # algo
+        (fake_in, fake_out, 4, 4, 4, 4, 1.0, 2, 5, c, 1, 1),    # valu fp16
+        (fake_in, C.c_void_p(0x10010), 4, 4, 4, 4, 1.0, 2, 5, c, 0, 0),  # overlap
+        (fake_in, fake_out, -1, 4, 4, 4, 1.0, 2, 5, c, 0, 0),   # negative H
+    ]
+    for a in cases:
+        st = lib.fobf_filter(*a, None)
+        assert st == F.fobf.EINVAL, (a, F.last_error())
+        assert F.last_error()
+    nan_c = (C.c_double * 32)(float("nan"), *([0.0] * 31))
+    st = lib.fobf_filter(fake_in, fake_out, 4, 4, 4, 4, 1.0, 1, 5, nan_c, 0, 0,
+                         None)
+    assert st == F.fobf.EINVAL
+    # empty image: nothing to do, nothing touched
+    assert lib.fobf_filter(None, None, 0, 5, 5, 5, 1.0, 2, 5, c, 0, 0, None) == 0
+
+
+def test_radius_rule_matches_oracle():
+    """ceil(3 theta) computed the same way on both sides (double)."""
+    import paper_1811_02168_amd as F  # noqa: F401
+    for theta in [0.1, 1 / 3, 2.0, 10 / 3, 3.0, 5.0, 10.0, 16.0]:
+        assert O.spatial_radius(theta) == math.ceil(3.0 * theta)
