@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Benchmark of the Fourier bilateral filter on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): one
+4096x4096 synthetic 8-bit-like image (Voronoi + ramp + noise, 256 cells,
+seed 1003), theta = 10 (61-tap truncated Gaussian), K = 8, R = 255, and the
+three range widths sigma = 20, 50, 100.  One step is the whole hot path for
+all three sigmas: host fit lookup (float64, cached), coefficient upload in
+the kernel arguments, and the fused filter kernel.  Inputs are resident in
+HBM before timing starts.
+
+`value` is the float32 ("plain") throughput; the fp16- and bf16-staged
+("mixed") forms are timed the same way and reported under "mixed", each
+with its max-abs and PSNR against the FP64 oracle on sampled pixels.
+
+Prints ONE JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X dense fp32 (vector and matrix)
+PEAK_HBM_GBS = 8000.0
+FLOP_PER_PX = None            # set from theta, K: 4 (2r+1)(4K-3)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--modes", default="fp32,fp16,bf16")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="for rocprofv3 counter passes: one 256 MiB device "
+                    "copy (calibrates FETCH_SIZE/WRITE_SIZE), then one launch "
+                    "per precision of the C3 filter at sigma=50, then exit")
+    return ap.parse_args()
+
+
+def profile_run(modes):
+    import numpy as np
+    import torch
+
+    import paper_1811_02168_amd as F
+    import workloads
+
+    cfg = workloads.C3
+    dev = torch.device("cuda")
+    a = torch.ones(64 << 20, dtype=torch.float32, device=dev)     # 256 MiB
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    img = torch.from_numpy(cfg.image().astype(np.float32)).to(dev)
+    out = torch.empty_like(img)
+    coef = F.fit(cfg.R, 50.0, cfg.K, eps=cfg.eps)
+    for m in modes:
+        F.filter(img, cfg.theta, cfg.K, coef.T, coef.c, prec=m, out=out)
+        torch.cuda.synchronize()
+        print(f"[profile-run] {m} done", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("fobf_mfma.hip", "fobf_api.cpp"):
+        with open(os.path.join(ROOT, "paper_1811_02168_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel_key, launches_bytes_alg):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when that summary is missing or was taken from other kernel code."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(kernel_key)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.profile_run:
+        profile_run([m for m in args.modes.split(",") if m])
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                          f"--gpus {args.gpus} is not supported"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1811_02168_amd as F
+    import workloads
+
+    cfg = workloads.C3
+    theta, K, R = cfg.theta, cfg.K, cfg.R
+    r = math.ceil(3 * theta)
+    flop_px = 4 * (2 * r + 1) * (4 * K - 3)
+    H, W = cfg.H, cfg.W
+    npx = H * W
+    f = cfg.image()
+    dev = torch.device("cuda")
+    img = torch.from_numpy(f.astype(np.float32)).to(dev)
+    outs = {s: torch.empty_like(img) for s in cfg.sigmas}
+    stream = torch.cuda.current_stream()
+
+    def step(prec):
+        for s in cfg.sigmas:
+            coef = F.fit(R, s, K, eps=cfg.eps)         # cached host fit
+            F.filter(img, theta, K, coef.T, coef.c, prec=prec, out=outs[s])
+
+    def timed(prec, steps, warmup):
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ev[i][0].record(stream)
+            step(prec)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+        ms_step = wall * 1e3 / steps
+        nimg = len(cfg.sigmas)
+        return {
+            "ms_per_step": ms_step,
+            "kernel_ms": gpu_ms / nimg,          # average per launch
+            "value": nimg * npx / (ms_step * 1e-3) / 1e6,
+        }
+
+    for s in cfg.sigmas:                               # fits outside timing
+        F.fit(R, s, K, eps=cfg.eps)
+    modes = [m for m in args.modes.split(",") if m]
+    if args.no_mixed:
+        modes = ["fp32"]
+    res = {}
+    for m in modes:
+        res[m] = timed(m, args.steps, args.warmup)
+        print(f"[bench] {m}: {res[m]}", file=sys.stderr, flush=True)
+
+    main_res = res["fp32"]
+    achieved = flop_px * npx / (main_res["kernel_ms"] * 1e-3) / 1e12
+    alg_bytes = 8 * npx
+    traffic = traffic_record("mfma_f32_kernel_c3", alg_bytes)
+    roofline = {
+        "bound": "mfma",
+        "achieved": round(achieved, 2),
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+        "traffic": traffic,
+        "kernel": "mfma_f32_kernel<DV=5>",
+        "kernel_ms": round(main_res["kernel_ms"], 4),
+        "flop_per_px": flop_px,
+        "hbm_gbs_algorithmic": round(alg_bytes / (main_res["kernel_ms"] * 1e-3) / 1e9, 1),
+    }
+
+    mixed = {}
+    for m in modes:
+        if m == "fp32":
+            continue
+        a = flop_px * npx / (res[m]["kernel_ms"] * 1e-3) / 1e12
+        mixed[m + "_stage"] = {
+            "value": round(res[m]["value"], 1), "unit": "Mpix/s",
+            "ms_per_step": round(res[m]["ms_per_step"], 4),
+            "kernel_ms": round(res[m]["kernel_ms"], 4),
+            "tflops_equiv": round(a, 2),
+            "frac_fp32_peak": round(a / PEAK_FP32_TFLOPS, 4)}
+
+    cpu = None
+    accuracy = None
+    if not args.no_cpu_baseline:
+        cpu, accuracy = cpu_baseline_leg(f, cfg, modes, outs, step, F, torch)
+
+    serving = None
+    if not args.no_serve and hasattr(F.lib, "fobf_serve_create"):
+        try:
+            from paper_1811_02168_amd import serving as S
+            serving = S.bench_serving(f, n=args.serve_requests)
+        except Exception as e:  # reported, never hidden
+            serving = {"error": repr(e)}
+
+    line = {
+        "metric": "Mpix/s FOBF K=8 theta=10 4096^2 (fp32 plain; mixed below)",
+        "value": round(main_res["value"], 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C3: 4096x4096 Voronoi+ramp+noise, theta=10 "
+                   "(61 taps), K=8, R=255, sigma in {20,50,100}; one step = "
+                   "3 filtered images", "images_per_step": len(cfg.sigmas),
+                   "H": H, "W": W, "theta": theta, "K": K,
+                   "sigmas": list(cfg.sigmas)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "mixed": mixed,
+        "accuracy_vs_fp64_oracle": accuracy,
+        "serving": serving,
+    }
+    print(json.dumps(line))
+
+
+def cpu_baseline_leg(f, cfg, modes, outs, step, F, torch):
+    """Times the FP64 oracle on a bounded sample of the workload and, with
+    the same oracle, measures each precision's error on sampled pixels."""
+    import numpy as np
+
+    import oracle as O
+
+    n = 2048
+    crop = f[:n, :n]
+    ref = O.fit(cfg.R, 50.0, cfg.K)
+    t0 = time.perf_counter()
+    O.fourier_direct(crop, cfg.theta, cfg.K, ref["T"], ref["c"])
+    dt = time.perf_counter() - t0
+    cpu = {"value": round(n * n / dt / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"fourier_direct (float64 numpy) on the top-left {n}x{n} "
+                     f"crop of the 4096^2 image, sigma=50, K={cfg.K}, "
+                     f"theta={cfg.theta}; one run, {dt:.1f} s",
+           "host_cpus": os.cpu_count()}
+
+    rng = np.random.default_rng(77)
+    H, W = f.shape
+    ys = np.concatenate([rng.integers(0, H, 400), [0, 0, H - 1, H - 1, 17, H - 5]])
+    xs = np.concatenate([rng.integers(0, W, 400), [0, W - 1, 0, W - 1, W - 3, 9]])
+    acc = {}
+    for m in modes:
+        step(m)
+        torch.cuda.synchronize()
+        worst, se, cnt = 0.0, 0.0, 0
+        for s in cfg.sigmas:
+            coef = F.fit(cfg.R, s, cfg.K, eps=cfg.eps)
+            got = outs[s].cpu().numpy()[ys, xs].astype(np.float64)
+            want, _, _ = O.brute_bf_points(f, cfg.theta,
+                                           O.cosine_series(coef.c, coef.T), ys, xs)
+            d = got - want
+            worst = max(worst, float(np.max(np.abs(d))))
+            se += float(np.sum(d * d))
+            cnt += len(d)
+        mse = se / cnt
+        acc[m] = {"maxabs": worst,
+                  "psnr_db": (10 * math.log10(255.0 ** 2 / mse)) if mse > 0 else None,
+                  "pixels": cnt}
+    return cpu, acc
+
+
+if __name__ == "__main__":
+    main()

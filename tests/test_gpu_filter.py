@@ -59,41 +59,48 @@ def fitted(sigma, K):
 
 
 ALGOS = ["valu", "mfma"]
+# (algorithm, precision) pairs under test, and their max-abs bounds
+MODES = [("valu", "fp32"), ("mfma", "fp32"), ("mfma", "fp16"), ("mfma", "bf16")]
+MODE_IDS = [f"{a}-{p}" for a, p in MODES]
 
 
-@pytest.mark.parametrize("algo", ALGOS)
-def test_c1_full(algo):
+def tol(prec):
+    return TOL_F32 if prec == "fp32" else TOL
+
+
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
+def test_c1_full(algo, prec):
     cfg = workloads.C1
     f = cfg.image()
     T, c = fitted(cfg.sigmas[0], cfg.K)
-    got = gpu_filter(f, cfg.theta, cfg.K, T, c, algo=algo)
+    got = gpu_filter(f, cfg.theta, cfg.K, T, c, prec=prec, algo=algo)
     s = compare(f, cfg.theta, cfg.K, T, c, got)
-    print("C1", algo, s)
-    assert s["maxabs"] <= TOL_F32
+    print("C1", algo, prec, s)
+    assert s["maxabs"] <= tol(prec)
 
 
-@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("sigma", workloads.C2.sigmas)
-def test_c2_crop(algo, sigma):
+def test_c2_crop(algo, prec, sigma):
     cfg = workloads.C2
     f = cfg.image()[100:400, 200:637]          # 300 x 437, ragged tiles
     T, c = fitted(sigma, cfg.K)
-    got = gpu_filter(f, cfg.theta, cfg.K, T, c, algo=algo)
+    got = gpu_filter(f, cfg.theta, cfg.K, T, c, prec=prec, algo=algo)
     s = compare(f, cfg.theta, cfg.K, T, c, got)
-    print("C2", algo, sigma, T, s)
-    assert s["maxabs"] <= TOL_F32
+    print("C2", algo, prec, sigma, T, s)
+    assert s["maxabs"] <= tol(prec)
 
 
-@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("sigma", workloads.C3.sigmas)
-def test_c3_crop(algo, sigma):
+def test_c3_crop(algo, prec, sigma):
     cfg = workloads.C3
     f = cfg.image()[1000:1321, 3000:3283]      # 321 x 283
     T, c = fitted(sigma, cfg.K)
-    got = gpu_filter(f, cfg.theta, cfg.K, T, c, algo=algo)
+    got = gpu_filter(f, cfg.theta, cfg.K, T, c, prec=prec, algo=algo)
     s = compare(f, cfg.theta, cfg.K, T, c, got)
-    print("C3crop", algo, sigma, T, s)
-    assert s["maxabs"] <= TOL_F32
+    print("C3crop", algo, prec, sigma, T, s)
+    assert s["maxabs"] <= tol(prec)
 
 
 EDGE = [
@@ -111,43 +118,58 @@ EDGE = [
 ]
 
 
-@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("H,W,theta,K,sigma", EDGE)
-def test_edge_cases(algo, H, W, theta, K, sigma):
+def test_edge_cases(algo, prec, H, W, theta, K, sigma):
     f = workloads.voronoi_image(H, W, max(2, (H * W) // 400), True, H * 1000 + W)
     T, c = fitted(sigma, K)
-    got = gpu_filter(f, theta, K, T, c, algo=algo, pad=5)
+    got = gpu_filter(f, theta, K, T, c, prec=prec, algo=algo, pad=5)
     s = compare(f, theta, K, T, c, got)
-    print("edge", algo, H, W, theta, K, T, s)
-    assert s["maxabs"] <= TOL_F32
+    print("edge", algo, prec, H, W, theta, K, T, s)
+    assert s["maxabs"] <= tol(prec)
 
 
-@pytest.mark.parametrize("algo", ALGOS)
-def test_non_integer_image_and_random_coefficients(algo):
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
+def test_non_integer_image_and_random_coefficients(algo, prec):
     """The library accepts any real f and any c (D may change sign)."""
     rng = np.random.default_rng(9)
     f = rng.uniform(0, 255, size=(61, 77))
     c = np.array([0.5, 0.3, 0.15, 0.05])
-    got = gpu_filter(f, 1.8, 4, 90, c, algo=algo)
+    got = gpu_filter(f, 1.8, 4, 90, c, prec=prec, algo=algo)
     s = compare(f, 1.8, 4, 90, c, got)
-    assert s["maxabs"] <= TOL_F32
+    assert s["maxabs"] <= tol(prec)
 
 
-@pytest.mark.parametrize("algo", ALGOS)
-def test_deterministic(algo):
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
+def test_deterministic(algo, prec):
     f = workloads.C2.image()[:200, :300]
     T, c = fitted(30.0, 6)
-    a = gpu_filter(f, 5.0, 6, T, c, algo=algo)
-    b = gpu_filter(f, 5.0, 6, T, c, algo=algo)
+    a = gpu_filter(f, 5.0, 6, T, c, prec=prec, algo=algo)
+    b = gpu_filter(f, 5.0, 6, T, c, prec=prec, algo=algo)
     assert np.array_equal(a, b)
 
 
-def test_constant_image_fixed_point():
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
+def test_constant_image_fixed_point(algo, prec):
     f = np.full((77, 91), 143.0)
-    for algo in ALGOS:
-        T, c = fitted(30.0, 6)
-        got = gpu_filter(f, 4.0, 6, T, c, algo=algo)
-        assert np.max(np.abs(got - 143.0)) < 1e-3
+    T, c = fitted(30.0, 6)
+    got = gpu_filter(f, 4.0, 6, T, c, prec=prec, algo=algo)
+    assert np.max(np.abs(got - 143.0)) < (1e-3 if prec == "fp32" else 0.05)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_staged_against_fp32_kernel(prec):
+    """The mixed-precision forms stay within the contract of the plain
+    float32 kernel's output (C3 parameters, 512^2 crop)."""
+    cfg = workloads.C3
+    f = cfg.image()[2000:2512, 500:1012]
+    for sigma in cfg.sigmas:
+        T, c = fitted(sigma, cfg.K)
+        a = gpu_filter(f, cfg.theta, cfg.K, T, c, prec="fp32", algo="mfma")
+        b = gpu_filter(f, cfg.theta, cfg.K, T, c, prec=prec, algo="mfma")
+        d = float(np.max(np.abs(a - b)))
+        print("staged vs fp32", prec, sigma, d)
+        assert d <= TOL
 
 
 def sample_points(H, W, n, seed):
@@ -161,19 +183,19 @@ def sample_points(H, W, n, seed):
     return np.array(ys), np.array(xs)
 
 
-@pytest.mark.parametrize("algo", ALGOS)
-def test_c3_full_size_sampled(algo):
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
+def test_c3_full_size_sampled(algo, prec):
     """4096^2, theta=10, K=8 (the benchmark launch): sampled outputs against
     eq. (1) evaluated pixel by pixel with the fitted cosine series."""
     cfg = workloads.C3
     f = cfg.image()
     for sigma in cfg.sigmas:
         T, c = fitted(sigma, cfg.K)
-        got = gpu_filter(f, cfg.theta, cfg.K, T, c, algo=algo)
+        got = gpu_filter(f, cfg.theta, cfg.K, T, c, prec=prec, algo=algo)
         ys, xs = sample_points(*f.shape, 600, int(sigma))
         ref, num, den = O.brute_bf_points(f, cfg.theta, O.cosine_series(c, T),
                                           ys, xs)
         err = np.abs(got[ys, xs] - ref)
-        print("C3 full", algo, sigma, T, float(err.max()))
-        assert float(err.max()) <= TOL_F32
+        print("C3 full", algo, prec, sigma, T, float(err.max()))
+        assert float(err.max()) <= tol(prec)
         assert np.all(np.isfinite(got))
