@@ -89,12 +89,14 @@ struct Img {
 // =========================================================================
 
 // One channel group over this wave's strip: G = 1 is {f} (k = 0, no trig),
-// G = 4 is {C f, S f, C, S} of frequency k >= 1.
+// G = 4 is {C f, S f, C, S} of frequency k >= 1.  Bt / At are the
+// horizontal / vertical Toeplitz slices, one float per lane per MFMA step,
+// precomputed in LDS.  The image values of the next 16-row block are
+// loaded while the current block is on the matrix cores.
 template <int DV, int G>
 __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
-                                          int nblk, const float* tbl, float* Ns,
-                                          float* Ds, int lane) {
-  const float* gS = tbl;
+                                          int nblk, const float* tbl, const float* Bt,
+                                          const float* At, float* Ns, float* Ds, int lane) {
   const float* cS = tbl + 64;
   const int r = im.r;
   const int SH = (MSTRIP + 2 * r + 3) >> 2;   // horizontal 4-column steps
@@ -102,33 +104,47 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
   const int lk = lane >> 4;
   const float kinv = static_cast<float>(k) * im.inv_period;
   const float ck = cS[k];
-
-  float Bh[4 * DV];
-#pragma unroll
-  for (int s = 0; s < 4 * DV; ++s) Bh[s] = tap(gS, 4 * s + lk - r - li, r);
-  float Av[DV][4];
-#pragma unroll
-  for (int d = 0; d < DV; ++d)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Av[d][v] = tap(gS, 16 * d + 4 * lk + v - r - li, r);
-
-  f4 ring[DV][G];
   const int QB = nblk + DV - 1;
   const int colbase = x0w - r + lk;
+  const int gxo = min(x0w + li, im.W - 1);
+
+  f4 ring[DV][G];
+  float fn[4 * DV];
+  {
+    const int row = y0 - r + li;
+    const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
+#pragma unroll
+    for (int s = 0; s < 4 * DV; ++s) fn[s] = rp[min(max(colbase + 4 * s, 0), im.W - 1)];
+  }
 
   for (int qq = 0; qq < QB; qq += DV) {
 #pragma unroll
     for (int u = 0; u < DV; ++u) {
       const int q = qq + u;
       if (q < QB) {
+        float fc[4 * DV];
+#pragma unroll
+        for (int s = 0; s < 4 * DV; ++s) fc[s] = fn[s];
+        const int pb = q - (DV - 1);
+        // output-pixel values for this block's fold (issued before the
+        // prefetch so that waiting for them does not wait for it)
+        float fo[4];
+        if (G == 4 && pb >= 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int gy = min(y0 + 16 * pb + 4 * lk + v, im.H - 1);
+            fo[v] = im.in[static_cast<size_t>(gy) * im.ld_in + gxo];
+          }
+        }
+        if (q + 1 < QB) {
+          const int row = y0 - r + 16 * (q + 1) + li;
+          const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
+#pragma unroll
+          for (int s = 0; s < 4 * DV; ++s) fn[s] = rp[min(max(colbase + 4 * s, 0), im.W - 1)];
+        }
         // ---- horizontal pass, H rows 16q .. 16q+15 of the strip ----
         const int row = y0 - r + 16 * q + li;
         const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
-        const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
-        float fv[4 * DV];
-#pragma unroll
-        for (int s = 0; s < 4 * DV; ++s)     // every load first (clamped, in bounds)
-          fv[s] = rp[min(max(colbase + 4 * s, 0), im.W - 1)];
         f4 acc[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
@@ -137,12 +153,13 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
           if (s < SH) {
             const bool in = rin && static_cast<unsigned>(colbase + 4 * s) <
                                        static_cast<unsigned>(im.W);
-            const float m = in ? 1.f : 0.f;
-            const float f = in ? fv[s] : 0.f;
+            const float f = in ? fc[s] : 0.f;
+            const float bh = Bt[s * 64 + lane];
             float a[G];
             if (G == 1) {
               a[0] = f;
             } else {
+              const float m = in ? 1.f : 0.f;
               float sn, cs;
               sincos_rev(kinv * f, &sn, &cs);
               a[0] = cs * f;
@@ -152,14 +169,13 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
             }
 #pragma unroll
             for (int g = 0; g < G; ++g)
-              acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g], Bh[s], acc[g], 0, 0, 0);
+              acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g], bh, acc[g], 0, 0, 0);
           }
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) ring[u][g] = acc[g];
 
-        // ---- vertical pass, output block pb = q - DV + 1 ----
-        const int pb = q - (DV - 1);
+        // ---- vertical pass, output block pb ----
         if (pb >= 0) {
           f4 vacc[G];
 #pragma unroll
@@ -168,25 +184,23 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
           for (int d = 0; d < DV; ++d) {
             const int slot = (u + 1 + d) % DV;
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+            for (int v = 0; v < 4; ++v) {
+              const float av = At[(d * 4 + v) * 64 + lane];
 #pragma unroll
               for (int g = 0; g < G; ++g)
-                vacc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(Av[d][v], ring[slot][g][v],
-                                                               vacc[g], 0, 0, 0);
+                vacc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ring[slot][g][v], vacc[g],
+                                                               0, 0, 0);
+            }
           }
           // ---- fold into N, D with the output pixel's own trig ----
-          const int gx = min(x0w + li, im.W - 1);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int orow = 16 * pb + 4 * lk + v;
-            const int idx = orow * MSTRIP + li;
+            const int idx = (pb * 4 + v) * 64 + lane;
             if (G == 1) {
               Ns[idx] = fmaf(ck, vacc[0][v], Ns[idx]);
             } else {
-              const int gy = min(y0 + orow, im.H - 1);
-              const float fo = im.in[static_cast<size_t>(gy) * im.ld_in + gx];
               float sn, cs;
-              sincos_rev(kinv * fo, &sn, &cs);
+              sincos_rev(kinv * fo[v], &sn, &cs);
               Ns[idx] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), Ns[idx]);
               Ds[idx] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), Ds[idx]);
             }
@@ -197,57 +211,105 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
   }
 }
 
-// N = 0, D = c_0 W(i) for the wave's strip of nblk 16-row blocks
+// Per-lane N and D of the wave's strip live in LDS at ((pb*4 + v)*64 +
+// lane) for output pixel (row 16 pb + 4 (lane/16) + v, column lane % 16):
+// one 16-row block is 256 consecutive floats, so a wave's access is
+// bank-conflict free.
+// N = 0, D = c_0 W(i).
 __device__ __forceinline__ void init_nd(const Img& im, const float* tbl, int x0w, int y0,
-                                        int rows, float* Ns, float* Ds, int lane) {
+                                        int nblk, float* Ns, float* Ds, int lane) {
   const float* cS = tbl + 64;
   const float* sS = tbl + 96;
   const float wx = edge_weight(sS, x0w + (lane & 15), im.W, im.r);
-  for (int row = lane >> 4; row < rows; row += 4) {
-    const float wy = edge_weight(sS, y0 + row, im.H, im.r);
-    Ns[row * MSTRIP + (lane & 15)] = 0.f;
-    Ds[row * MSTRIP + (lane & 15)] = cS[0] * wx * wy;
+  for (int pb = 0; pb < nblk; ++pb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float wy = edge_weight(sS, y0 + 16 * pb + 4 * (lane >> 4) + v, im.H, im.r);
+      const int idx = (pb * 4 + v) * 64 + lane;
+      Ns[idx] = 0.f;
+      Ds[idx] = cS[0] * wx * wy;
+    }
+}
+
+__device__ __forceinline__ void store_nd(const Img& im, int x0w, int y0, int nblk,
+                                         const float* Ns, const float* Ds, int lane,
+                                         float shift = 0.f) {
+  const int gx = x0w + (lane & 15);
+  for (int pb = 0; pb < nblk; ++pb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gy = y0 + 16 * pb + 4 * (lane >> 4) + v;
+      const int idx = (pb * 4 + v) * 64 + lane;
+      if (gy < im.H && gx < im.W)
+        im.out[static_cast<size_t>(gy) * im.ld_out + gx] = Ns[idx] / Ds[idx] + shift;
+    }
+}
+
+// Toeplitz slices as per-lane LDS tables: Bt[s][lane] (horizontal,
+// 4*DV steps) and At[d*4+v][lane] (vertical, DV blocks x 4 rows).
+template <int DV>
+__device__ __forceinline__ void build_f32_tables(const float* gS, int r, float* Bt, float* At) {
+  for (int i = threadIdx.x; i < 4 * DV * 64; i += blockDim.x) {
+    const int s = i >> 6, l = i & 63;
+    Bt[i] = tap(gS, 4 * s + (l >> 4) - r - (l & 15), r);
+    const int d = s >> 2, v = s & 3;
+    At[i] = tap(gS, 16 * d + 4 * (l >> 4) + v - r - (l & 15), r);
   }
 }
 
-__device__ __forceinline__ void store_nd(const Img& im, int x0w, int y0, int rows,
-                                         const float* Ns, const float* Ds, int lane,
-                                         float shift = 0.f) {
-  for (int row = lane >> 4; row < rows; row += 4) {
-    const int gy = y0 + row, gx = x0w + (lane & 15);
-    if (gy < im.H && gx < im.W) {
-      const int idx = row * MSTRIP + (lane & 15);
-      im.out[static_cast<size_t>(gy) * im.ld_out + gx] = Ns[idx] / Ds[idx] + shift;
-    }
-  }
+// XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round-robin
+// (block L runs on XCD L % 8); each XCD is given a contiguous run of tiles,
+// walked in panels 8 tiles wide, so the tiles resident on one XCD share
+// their halos in that XCD's L2.  Returns false for padding blocks.
+__device__ __forceinline__ bool tile_of_block(int L, int nblocks, int ntx, int nty, int* tx,
+                                              int* ty) {
+  const int per = nblocks >> 3;
+  const int t = (L & 7) * per + (L >> 3);
+  if (t >= ntx * nty) return false;
+  constexpr int PW = 8;
+  const int panel = t / (PW * nty);
+  const int rem = t - panel * PW * nty;
+  const int pw = min(PW, ntx - panel * PW);
+  *ty = rem / pw;
+  *tx = panel * PW + (rem - *ty * pw);
+  return true;
 }
 
 template <int DV>
 __device__ __forceinline__ void f32_tile(const Img& im, int tx, int ty, int nblk,
-                                         const float* tbl, float* nd) {
+                                         const float* tbl, const float* Bt, const float* At,
+                                         float* nd) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int TYo = 16 * nblk;
-  float* Ns = nd + wave * 2 * TYo * MSTRIP;
-  float* Ds = Ns + TYo * MSTRIP;
+  float* Ns = nd + wave * 2 * nblk * 256;
+  float* Ds = Ns + nblk * 256;
   const int x0w = tx * (MWAVES * MSTRIP) + wave * MSTRIP;
-  const int y0 = ty * TYo;
-  init_nd(im, tbl, x0w, y0, TYo, Ns, Ds, lane);
-  f32_group<DV, 1>(im, 0, x0w, y0, nblk, tbl, Ns, Ds, lane);
-  for (int k = 1; k < im.K; ++k) f32_group<DV, 4>(im, k, x0w, y0, nblk, tbl, Ns, Ds, lane);
-  store_nd(im, x0w, y0, TYo, Ns, Ds, lane);
+  const int y0 = ty * 16 * nblk;
+  init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);
+  f32_group<DV, 1>(im, 0, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+  for (int k = 1; k < im.K; ++k)
+    f32_group<DV, 4>(im, k, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+  store_nd(im, x0w, y0, nblk, Ns, Ds, lane);
 }
 
 template <int DV>
 __global__ __launch_bounds__(MTHREADS, (DV <= 5 ? 2 : 1)) void mfma_f32_kernel(ImageParams p,
                                                                          int nblk) {
   extern __shared__ float lds[];
+  const int ntx = (p.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP);
+  const int nty = (p.H + 16 * nblk - 1) / (16 * nblk);
+  int tx, ty;
+  if (!tile_of_block(blockIdx.x, gridDim.x, ntx, nty, &tx, &ty)) return;
   float* tbl = lds;
-  float* nd = lds + LDS_TABLE;
+  float* Bt = lds + LDS_TABLE;
+  float* At = Bt + 4 * DV * 64;
+  float* nd = At + 4 * DV * 64;
   FOBF_LOAD_TABLES(p, tbl);
+  __syncthreads();
+  build_f32_tables<DV>(tbl, p.r, Bt, At);
   const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
   __syncthreads();
-  f32_tile<DV>(im, blockIdx.x, blockIdx.y, nblk, tbl, nd);
+  f32_tile<DV>(im, tx, ty, nblk, tbl, Bt, At, nd);
 }
 
 // =========================================================================
@@ -456,7 +518,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int orow = 16 * pb + 4 * lk + v;
-            const int idx = orow * MSTRIP + li;
+            const int idx = (pb * 4 + v) * 64 + lane;
             if (G == 1) {
               Ns[idx] = fmaf(ck, vacc[0][v], Ns[idx]);
             } else {
@@ -480,8 +542,8 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int TYo = 16 * nblk;
-  float* Ns = nd + wave * 2 * TYo * MSTRIP;
-  float* Ds = Ns + TYo * MSTRIP;
+  float* Ns = nd + wave * 2 * nblk * 256;
+  float* Ds = Ns + nblk * 256;
   const int x0 = tx * (MWAVES * MSTRIP);
   const int y0 = ty * TYo;
   const int x0w = x0 + wave * MSTRIP;
@@ -490,11 +552,11 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
   // magnitudes rounded to the staging type shrink to the local contrast.
   const float shift = im.in[static_cast<size_t>(min(y0 + TYo / 2, im.H - 1)) * im.ld_in +
                             min(x0 + MWAVES * MSTRIP / 2, im.W - 1)];
-  init_nd(im, tbl, x0w, y0, TYo, Ns, Ds, lane);
+  init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);
   staged_group<OT, DV, 1>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
   for (int k = 1; k < im.K; ++k)
     staged_group<OT, DV, 4>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
-  store_nd(im, x0w, y0, TYo, Ns, Ds, lane, shift);
+  store_nd(im, x0w, y0, nblk, Ns, Ds, lane, shift);
 }
 
 template <typename OT, int DV>
@@ -506,13 +568,17 @@ constexpr size_t staged_buf_bytes() {
 template <typename OT, int DV>
 __global__ __launch_bounds__(MTHREADS) void mfma_staged_kernel(ImageParams p, int nblk) {
   extern __shared__ float lds[];
+  const int ntx = (p.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP);
+  const int nty = (p.H + 16 * nblk - 1) / (16 * nblk);
+  int tx, ty;
+  if (!tile_of_block(blockIdx.x, gridDim.x, ntx, nty, &tx, &ty)) return;
   float* tbl = lds;
   OT* sbuf = reinterpret_cast<OT*>(lds + LDS_TABLE);
   float* nd = lds + LDS_TABLE + staged_buf_bytes<OT, DV>() / sizeof(float);
   FOBF_LOAD_TABLES(p, tbl);
   const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
   __syncthreads();
-  staged_tile<OT, DV>(im, blockIdx.x, blockIdx.y, nblk, tbl, sbuf, nd);
+  staged_tile<OT, DV>(im, tx, ty, nblk, tbl, sbuf, nd);
 }
 
 // ------------------------------------------------------------------ host --
@@ -521,6 +587,13 @@ template <typename KernelT>
 void allow_big_lds(KernelT kernel) {
   hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+// 1-D grid: tiles rounded up to a multiple of the 8 XCDs
+unsigned padded_blocks(const ImageParams& p, int nblk) {
+  const long ntx = (p.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP);
+  const long nty = (p.H + 16 * nblk - 1) / (16 * nblk);
+  return static_cast<unsigned>(((ntx * nty + 7) / 8) * 8);
 }
 
 fobf_status check_launch(const char* what) {
@@ -533,8 +606,9 @@ template <int DV>
 fobf_status launch_f32_dv(const ImageParams& p, int nblk, void* stream) {
   static const bool once = (allow_big_lds(mfma_f32_kernel<DV>), true);
   (void)once;
-  const size_t lds = sizeof(float) * (LDS_TABLE + static_cast<size_t>(MWAVES) * 2 * 16 * nblk * MSTRIP);
-  dim3 grid((p.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP), (p.H + 16 * nblk - 1) / (16 * nblk));
+  const size_t lds = sizeof(float) * (LDS_TABLE + 8 * DV * 64 +
+                                      static_cast<size_t>(MWAVES) * 2 * nblk * 256);
+  dim3 grid(padded_blocks(p, nblk));
   hipLaunchKernelGGL(mfma_f32_kernel<DV>, grid, dim3(MTHREADS), lds,
                      static_cast<hipStream_t>(stream), p, nblk);
   return check_launch("mfma_f32_kernel");
@@ -545,8 +619,8 @@ fobf_status launch_staged_dv(const ImageParams& p, int nblk, void* stream) {
   static const bool once = (allow_big_lds(mfma_staged_kernel<OT, DV>), true);
   (void)once;
   const size_t lds = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV>() +
-                     sizeof(float) * MWAVES * 2 * 16 * nblk * MSTRIP;
-  dim3 grid((p.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP), (p.H + 16 * nblk - 1) / (16 * nblk));
+                     sizeof(float) * MWAVES * 2 * nblk * 256;
+  dim3 grid(padded_blocks(p, nblk));
   hipLaunchKernelGGL((mfma_staged_kernel<OT, DV>), grid, dim3(MTHREADS), lds,
                      static_cast<hipStream_t>(stream), p, nblk);
   return check_launch("mfma_staged_kernel");
