@@ -140,19 +140,42 @@ typedef struct {
 
 /*
  * fobf_filter_batch -- filter n independent images of different sizes and
- * parameters in ONE persistent launch: every workgroup pulls output tiles
+ * parameters with persistent launches: every workgroup pulls output tiles
  * from a shared queue that spans all jobs (work stealing), so small and
- * large images, and different radii and orders, share the machine.
+ * large images, and different radii and orders, share the machine.  All
+ * jobs of one precision and radius class (r <= 24, or 24 < r <= 48) go
+ * into ONE launch; a batch of one precision and class is one launch.
  *
- * jobs      host array of n jobs (read before return).
+ * jobs      host array of n jobs (read before return; the job table is
+ *           copied through a library-owned pinned buffer).
  * d_work    device workspace of at least fobf_batch_workspace_size(n)
- *           bytes, caller-owned, not used by another call until this
- *           call's work on the stream has finished.
- * Same rules per job as fobf_filter.  n == 0 is a no-op.
+ *           bytes, 256-byte aligned, caller-owned, not used by another
+ *           call until this call's work on the stream has finished.
+ * Same rules per job as fobf_filter (algorithm: matrix cores).  Jobs with
+ * H == 0 or W == 0 are skipped; n == 0 is a no-op.
  */
 size_t fobf_batch_workspace_size(int n);
 fobf_status fobf_filter_batch(const fobf_job* jobs, int n, void* d_work,
                               size_t work_bytes, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Tile-shape autotuner.
+ *
+ * fobf_filter (FOBF_ALGO_AUTO) and fobf_filter_batch read a process-wide
+ * table that picks, per precision and radius class dv = ceil((16 + 2r)/16),
+ * the algorithm (float32: matrix cores or vector ALU) and the tile height.
+ * fobf_autotune times every candidate for one precision on an H x W image
+ * of order K on the device (it allocates two temporary H x W buffers and
+ * synchronises `hip_stream`) and records the fastest; until then built-in
+ * defaults apply.  The table can be saved to and loaded from a text file.
+ * ---------------------------------------------------------------------- */
+fobf_status fobf_autotune(int prec, int H, int W, int K, void* hip_stream);
+fobf_status fobf_tune_save(const char* path);
+fobf_status fobf_tune_load(const char* path);
+fobf_status fobf_tune_reset(void);
+/* The choice the table makes for (prec, theta): *algo is a fobf_algo,
+ * *nblk the tile height in 16-row blocks. */
+fobf_status fobf_tune_get(int prec, double theta, int* algo, int* nblk);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching.
@@ -176,9 +199,11 @@ typedef struct {
 } fobf_serve_cfg;
 
 typedef struct {
-  const float* h_in;        /* host image H x W, row-major, dense          */
+  const float* h_in;        /* host image H x W, row-major; read while the */
+                            /* request is in flight                        */
   float* h_out;             /* host output H x W; alive until polled done  */
   int H, W;
+  int ld_in, ld_out;        /* host leading dimensions (0 = W)             */
   double theta, sigma;
   int K;                    /* order (>=1)                                 */
   int prec;                 /* fobf_prec                                   */
@@ -197,7 +222,18 @@ fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req,
  * status (copied into *res too) or FOBF_EBUSY while it is pending. */
 fobf_status fobf_serve_poll(fobf_server* s, uint64_t ticket, int wait,
                             fobf_result* res);
+/* Requests still queued when the server is destroyed complete with
+ * FOBF_ECANCELED; work already on the device finishes first.  Tickets are
+ * invalid afterwards. */
 fobf_status fobf_serve_destroy(fobf_server* s);
+
+typedef struct {
+  uint64_t submitted, completed, failed, batches;
+  size_t peak_bytes_inflight;   /* never exceeds cfg.hbm_budget_bytes      */
+  int peak_inflight;            /* never exceeds cfg.max_inflight          */
+  int coef_entries;             /* distinct (R, sigma, K) fits on device   */
+} fobf_serve_stats;
+fobf_status fobf_serve_get_stats(fobf_server* s, fobf_serve_stats* out);
 
 /* Test hook: the next `count` device submissions of this server report a
  * HIP error without launching anything (fault injection from the host). */

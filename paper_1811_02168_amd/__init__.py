@@ -2,11 +2,13 @@
 (include/fobf.h) with a thin ctypes binding.  Importing the package loads
 libfobf.so and fails loudly if it has not been built."""
 from .fobf import (ALGO_AUTO, ALGO_MFMA, ALGO_VALU, BF16_STAGE, FP16_STAGE,
-                   FP32, KMAX, RMAX, Coef, FobfError, Server,
+                   FP32, KMAX, RMAX, Coef, FobfError, Server, autotune,
                    batch_workspace_size, filter, filter_batch, fit,
-                   fit_samples, last_error, lib, make_job)
+                   fit_samples, last_error, lib, make_job, tune_get,
+                   tune_load, tune_reset, tune_save)
 
 __all__ = ["ALGO_AUTO", "ALGO_MFMA", "ALGO_VALU", "BF16_STAGE", "FP16_STAGE",
-           "FP32", "KMAX", "RMAX", "Coef", "FobfError", "Server",
+           "FP32", "KMAX", "RMAX", "Coef", "FobfError", "Server", "autotune",
            "batch_workspace_size", "filter", "filter_batch", "fit",
-           "fit_samples", "last_error", "lib", "make_job"]
+           "fit_samples", "last_error", "lib", "make_job", "tune_get",
+           "tune_load", "tune_reset", "tune_save"]

@@ -23,6 +23,7 @@ SOURCES = [
     "fobf_valu.hip",
     "fobf_mfma.hip",
     "fobf_batch.hip",
+    "fobf_tune.hip",
     "fobf_serve.cpp",
 ]
 

@@ -98,9 +98,11 @@ extern "C" fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W
   if (H == 0 || W == 0) return FOBF_OK;
   ImageParams p;
   make_params(p, d_in, d_out, H, W, ld_in, ld_out, theta, K, T, c);
-  if (algo == FOBF_ALGO_AUTO) algo = auto_algo(p.r, K, prec);
+  const int dv = (16 + 2 * p.r + 15) / 16;
+  const TuneChoice tc = tuned(prec, dv);
+  if (algo == FOBF_ALGO_AUTO) algo = (prec == FOBF_FP32) ? tc.algo : FOBF_ALGO_MFMA;
   if (algo == FOBF_ALGO_VALU) return launch_valu(p, hip_stream);
-  return launch_mfma(p, prec, hip_stream);
+  return launch_mfma(p, prec, tc.nblk, hip_stream);
 }
 
 extern "C" const char* fobf_last_error(void) { return fobf::error_cstr(); }

@@ -1,0 +1,290 @@
+// Batched filtering: many images of different sizes, radii, orders and
+// coefficients in one persistent launch.
+//
+// The host lays the jobs out in a device table, largest first, each with
+// its range of global tile indices.  A grid sized to fill the machine once
+// (CUs x resident workgroups) then loops: a workgroup takes the next tile
+// index from a shared counter (atomicAdd), finds its job by binary search
+// over the tile ranges, loads that job's tables into LDS (only when the job
+// changes), and runs the same tile body as the single-image kernels.  Small
+// and large images, and cheap and costly radii, so share the machine
+// instead of serialising behind one another; every workgroup exits when the
+// counter passes the last tile.
+//
+// One launch serves all jobs of one precision whose radius class fits the
+// kernel: DV = ceil((16 + 2r) / 16) <= 4 (r <= 24) or 5 <= DV <= 7 (r <= 48).
+// The float32 body runs with 4*DV horizontal steps (Toeplitz slices past
+// the band are zero), so one instantiation covers a whole radius class.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "fobf_tiles.h"
+
+namespace fobf {
+
+struct BatchJob {
+  ImageParams p;
+  int tile_begin;   // first global tile index of this job
+  int ntx, nty;     // tiles across / down
+  int nblk;         // 16-row blocks per tile (tile height 16 * nblk)
+  int dv;           // ceil((16 + 2r) / 16)
+  int pad_[3];
+};
+
+namespace {
+
+constexpr int BATCH_NBLK_MAX = 8;
+constexpr size_t COUNTER_BYTES = 256;   // one counter per launch, own line
+constexpr int MAX_LAUNCHES = 6;         // 3 precisions x 2 radius classes
+
+__global__ void reset_counter(int* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+}
+
+template <int PREC, int DVLO, int DVHI>
+__global__ __launch_bounds__(MTHREADS, 1) void batch_kernel(const BatchJob* __restrict__ jobs,
+                                                            int njobs, int total,
+                                                            int* __restrict__ counter) {
+  extern __shared__ float lds[];
+  __shared__ int s_tile;
+  float* tbl = lds;
+  int cur = -1;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_tile;
+    if (t >= total) break;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const BatchJob* J = jobs + lo;
+    const int lt = t - J->tile_begin;
+    const int ty = lt / J->ntx;
+    const int tx = lt - ty * J->ntx;
+    const int nblk = J->nblk;
+    const int dv = J->dv;
+    if (lo != cur) {
+      FOBF_LOAD_TABLES(J->p, tbl);
+      cur = lo;
+    }
+    __syncthreads();
+    const Img im{J->p.in, J->p.out, J->p.H, J->p.W, J->p.ld_in, J->p.ld_out,
+                 J->p.r, J->p.K, J->p.inv_period};
+    if constexpr (PREC == FOBF_FP32) {
+      float* Bt = lds + LDS_TABLE;
+      float* At = Bt + 4 * DVHI * 64;
+      float* nd = At + 4 * DVHI * 64;
+      switch (dv) {
+#define FOBF_F32_CASE(D)                                              \
+  case D:                                                             \
+    if constexpr (D >= DVLO && D <= DVHI) {                           \
+      build_f32_tables<4 * D>(tbl, im.r, Bt, At);                     \
+      __syncthreads();                                                \
+      f32_tile<4 * D>(im, tx, ty, nblk, tbl, Bt, At, nd);             \
+    }                                                                 \
+    break;
+        FOBF_F32_CASE(2)
+        FOBF_F32_CASE(3)
+        FOBF_F32_CASE(4)
+        FOBF_F32_CASE(5)
+        FOBF_F32_CASE(6)
+        FOBF_F32_CASE(7)
+#undef FOBF_F32_CASE
+        default: break;
+      }
+    } else {
+      typedef typename std::conditional<PREC == FOBF_FP16_STAGE, _Float16, __bf16>::type OT;
+      OT* sbuf = reinterpret_cast<OT*>(lds + LDS_TABLE);
+      float* nd = lds + LDS_TABLE + staged_buf_bytes<OT, DVHI>() / sizeof(float);
+      switch (dv) {
+#define FOBF_ST_CASE(D)                                               \
+  case D:                                                             \
+    if constexpr (D >= DVLO && D <= DVHI) staged_tile<OT, D>(im, tx, ty, nblk, tbl, sbuf, nd); \
+    break;
+        FOBF_ST_CASE(2)
+        FOBF_ST_CASE(3)
+        FOBF_ST_CASE(4)
+        FOBF_ST_CASE(5)
+        FOBF_ST_CASE(6)
+        FOBF_ST_CASE(7)
+#undef FOBF_ST_CASE
+        default: break;
+      }
+    }
+    __syncthreads();   // tile done before s_tile and the tables are rewritten
+  }
+}
+
+// LDS of a batch launch besides the per-wave N/D blocks
+template <int PREC, int DVHI>
+constexpr size_t batch_fixed_lds() {
+  if (PREC == FOBF_FP32) return sizeof(float) * (LDS_TABLE + 8 * DVHI * 64);
+  if (PREC == FOBF_FP16_STAGE) return sizeof(float) * LDS_TABLE + staged_buf_bytes<_Float16, DVHI>();
+  return sizeof(float) * LDS_TABLE + staged_buf_bytes<__bf16, DVHI>();
+}
+
+// tallest tile (16-row blocks) whose N/D still fits the 160 KB of LDS
+template <int PREC, int DVHI>
+constexpr int batch_nblk_cap() {
+  constexpr size_t room = 160 * 1024 - 256 - batch_fixed_lds<PREC, DVHI>();
+  constexpr int nb = static_cast<int>(room / (sizeof(float) * MWAVES * 2 * 256));
+  return nb < BATCH_NBLK_MAX ? nb : BATCH_NBLK_MAX;
+}
+
+template <int PREC, int DVHI>
+size_t batch_lds_bytes() {
+  return batch_fixed_lds<PREC, DVHI>() +
+         sizeof(float) * MWAVES * 2 * batch_nblk_cap<PREC, DVHI>() * 256;
+}
+
+template <int PREC, int DVLO, int DVHI>
+fobf_status launch_batch(const BatchJob* d_jobs, int njobs, int total, int* d_counter,
+                         void* stream) {
+  auto kern = batch_kernel<PREC, DVLO, DVHI>;
+  const size_t lds = batch_lds_bytes<PREC, DVHI>();
+  static int grid = 0;
+  static std::once_flag once;
+  std::call_once(once, [&]() {
+    // exactly the dynamic size (the kernel also holds a little static LDS)
+    hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    int dev = 0, cus = 0, occ = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, MTHREADS, lds);
+    grid = std::max(1, cus) * std::max(1, occ);
+  });
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, d_counter);
+  const int g = std::max(1, std::min(grid, total));
+  hipLaunchKernelGGL(kern, dim3(g), dim3(MTHREADS), lds, s, d_jobs, njobs, total, d_counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(FOBF_EHIP, std::string("batch_kernel launch: ") + hipGetErrorString(e));
+  return FOBF_OK;
+}
+
+typedef fobf_status (*BatchLauncher)(const BatchJob*, int, int, int*, void*);
+
+int class_nblk_cap(int prec, bool large) {
+  switch (prec) {
+    case FOBF_FP32: return large ? batch_nblk_cap<FOBF_FP32, 7>() : batch_nblk_cap<FOBF_FP32, 4>();
+    case FOBF_FP16_STAGE:
+      return large ? batch_nblk_cap<FOBF_FP16_STAGE, 7>() : batch_nblk_cap<FOBF_FP16_STAGE, 4>();
+    default:
+      return large ? batch_nblk_cap<FOBF_BF16_STAGE, 7>() : batch_nblk_cap<FOBF_BF16_STAGE, 4>();
+  }
+}
+
+BatchLauncher launcher_for(int prec, bool large) {
+  switch (prec) {
+    case FOBF_FP32: return large ? launch_batch<FOBF_FP32, 5, 7> : launch_batch<FOBF_FP32, 2, 4>;
+    case FOBF_FP16_STAGE:
+      return large ? launch_batch<FOBF_FP16_STAGE, 5, 7> : launch_batch<FOBF_FP16_STAGE, 2, 4>;
+    default:
+      return large ? launch_batch<FOBF_BF16_STAGE, 5, 7> : launch_batch<FOBF_BF16_STAGE, 2, 4>;
+  }
+}
+
+}  // namespace
+
+size_t batch_workspace_bytes(int n) {
+  return COUNTER_BYTES * MAX_LAUNCHES + sizeof(BatchJob) * static_cast<size_t>(std::max(n, 0));
+}
+
+// c_dev (optional, n entries): device rows the jobs' coefficients are read
+// from instead of the float32 copy in the job table (the server's
+// device-resident coefficient cache).
+fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t work_bytes,
+                              void* stream, const float* const* c_dev) {
+  if (n < 0) return fail(FOBF_EINVAL, "fobf_filter_batch: n < 0");
+  if (n == 0) return FOBF_OK;
+  if (!jobs) return fail(FOBF_EINVAL, "fobf_filter_batch: jobs is NULL");
+  if (!d_work) return fail(FOBF_EINVAL, "fobf_filter_batch: workspace is NULL");
+  if (work_bytes < batch_workspace_bytes(n))
+    return fail(FOBF_EINVAL, "fobf_filter_batch: workspace too small");
+  if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0)
+    return fail(FOBF_EINVAL, "fobf_filter_batch: workspace must be 256-byte aligned");
+  struct Entry {
+    BatchJob b;
+    double cost;
+    int cls;      // launch class: prec * 2 + large
+  };
+  std::vector<Entry> es;
+  es.reserve(n);
+  for (int i = 0; i < n; ++i) {
+    const fobf_job& j = jobs[i];
+    fobf_status st = validate_filter(j.d_in, j.d_out, j.H, j.W, j.ld_in, j.ld_out, j.theta, j.K,
+                                     j.T, j.c, j.prec, FOBF_ALGO_MFMA);
+    if (st != FOBF_OK) {
+      set_error("fobf_filter_batch: job " + std::to_string(i) + ": " + fobf_last_error());
+      return st;
+    }
+    if (j.H == 0 || j.W == 0) continue;
+    Entry e;
+    std::memset(&e.b, 0, sizeof(e.b));
+    make_params(e.b.p, j.d_in, j.d_out, j.H, j.W, j.ld_in, j.ld_out, j.theta, j.K, j.T, j.c);
+    e.b.p.c_dev = c_dev ? c_dev[i] : nullptr;
+    const int r = e.b.p.r;
+    e.b.dv = (16 + 2 * r + 15) / 16;
+    e.b.nblk = std::min(batch_tile_blocks(j.prec, e.b.dv, j.H),
+                        class_nblk_cap(j.prec, e.b.dv >= 5));
+    e.b.ntx = (j.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP);
+    e.b.nty = (j.H + 16 * e.b.nblk - 1) / (16 * e.b.nblk);
+    // cost of one tile ~ channels x (halo'd rows) x band
+    e.cost = static_cast<double>(4 * j.K - 3) * (e.b.nblk + e.b.dv - 1) * (2 * r + 1);
+    e.cls = j.prec * 2 + (e.b.dv >= 5 ? 1 : 0);
+    es.push_back(e);
+  }
+  // per class: largest tiles first (their tail is the hardest to hide)
+  std::stable_sort(es.begin(), es.end(), [](const Entry& a, const Entry& b) {
+    if (a.cls != b.cls) return a.cls < b.cls;
+    return a.cost * a.b.ntx * a.b.nty > b.cost * b.b.ntx * b.b.nty;
+  });
+  std::vector<BatchJob> table(es.size());
+  char* base = static_cast<char*>(d_work);
+  int* counters = reinterpret_cast<int*>(base);
+  BatchJob* d_table = reinterpret_cast<BatchJob*>(base + COUNTER_BYTES * MAX_LAUNCHES);
+  struct Launch {
+    int cls, first, count, total;
+  };
+  std::vector<Launch> launches;
+  for (size_t i = 0; i < es.size();) {
+    size_t k = i;
+    int tiles = 0;
+    while (k < es.size() && es[k].cls == es[i].cls) {
+      table[k] = es[k].b;
+      table[k].tile_begin = tiles;
+      tiles += es[k].b.ntx * es[k].b.nty;
+      ++k;
+    }
+    launches.push_back({es[i].cls, static_cast<int>(i), static_cast<int>(k - i), tiles});
+    i = k;
+  }
+  fobf_status up = upload_async(d_table, table.data(), sizeof(BatchJob) * table.size(), stream);
+  if (up != FOBF_OK) return up;
+  for (const Launch& L : launches) {
+    BatchLauncher fn = launcher_for(L.cls / 2, L.cls % 2 == 1);
+    int* ctr = reinterpret_cast<int*>(base + COUNTER_BYTES * L.cls);
+    fobf_status st = fn(d_table + L.first, L.count, L.total, ctr, stream);
+    if (st != FOBF_OK) return st;
+  }
+  (void)counters;
+  return FOBF_OK;
+}
+
+}  // namespace fobf
+
+extern "C" size_t fobf_batch_workspace_size(int n) { return fobf::batch_workspace_bytes(n); }
+
+extern "C" fobf_status fobf_filter_batch(const fobf_job* jobs, int n, void* d_work,
+                                         size_t work_bytes, void* hip_stream) {
+  return fobf::filter_batch_impl(jobs, n, d_work, work_bytes, hip_stream, nullptr);
+}

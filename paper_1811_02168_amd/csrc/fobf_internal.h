@@ -27,6 +27,7 @@ struct ImageParams {
   int K;             // order
   float inv_period;  // 1 / (2T + 1)
   int pad_;
+  const float* c_dev;       // when set: c_k read from this device array
   float c[FOBF_KMAX];       // c_k in float32
   float g[FOBF_RMAX + 1];   // taps g(0..r); g(-m) = g(m)
   float gsum[2 * FOBF_RMAX + 2];  // gsum[j] = sum_{m=-r}^{j-r-1} g(m), j=0..2r+1
@@ -42,12 +43,25 @@ fobf_status validate_filter(const float* in, const float* out, int H, int W,
                             int ld_in, int ld_out, double theta, int K, int T,
                             const double* c, int prec, int algo);
 
-// Launchers (fobf_valu.hip / fobf_mfma.hip).  Return FOBF_EHIP on launch
-// failure with the message set.
+// Launchers (fobf_valu.hip / fobf_mfma.hip).  nblk = 16-row blocks per
+// tile (tile height 16 nblk).  Return FOBF_EHIP on launch failure with the
+// message set.
 fobf_status launch_valu(const ImageParams& p, void* stream);
-fobf_status launch_mfma(const ImageParams& p, int prec, void* stream);
+fobf_status launch_mfma(const ImageParams& p, int prec, int nblk, void* stream);
 
-// Choice made by FOBF_ALGO_AUTO.
-int auto_algo(int r, int K, int prec);
+// Tuning table (fobf_tune.cpp): per precision and radius class dv =
+// ceil((16 + 2r) / 16), the algorithm and tile height chosen by
+// fobf_autotune, or the built-in defaults.
+struct TuneChoice {
+  int algo;   // FOBF_ALGO_VALU or FOBF_ALGO_MFMA
+  int nblk;   // 16-row blocks per tile
+};
+TuneChoice tuned(int prec, int dv);
+int batch_tile_blocks(int prec, int dv, int H);
+
+// Copies host bytes to the device on `stream` through a library-owned
+// pinned staging buffer, so the caller's host memory may be reused as soon
+// as this returns.  Never synchronises.
+fobf_status upload_async(void* dst, const void* src, size_t bytes, void* stream);
 
 }  // namespace fobf

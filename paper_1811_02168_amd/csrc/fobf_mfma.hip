@@ -1,300 +1,19 @@
-// Matrix-core (MFMA) paths of the K-term shiftable bilateral filter.
-//
-// The filter (Sec. II, first paragraph, with the cosine series of eq. (3)
-// as range kernel) is a sum over channels X of truncated-Gaussian spatial
-// convolutions, each weighted per output pixel i:
-//   channel        weight at i        into     (C_k = cos(2 pi k f/(2T+1)),
-//   f              c_0                N         S_k = sin(...), k = 1..K-1)
-//   C_k f, S_k f   c_k C_k(i), S_k(i) N
-//   C_k,   S_k     c_k C_k(i), S_k(i) D,   plus D += c_0 W(i), out = N / D.
-// Neighbours outside the image are excluded (every channel zero padded);
-// W(i) = Wy(y) Wx(x) is the sum of the in-image taps.
-//
-// Each convolution is two banded Toeplitz products on the matrix cores:
-//   horizontal  H[y][x] = sum_c X[y][c] Gh[c][x],  Gh[c][x] = g(c - x)
-//   vertical    V[y][x] = sum_h Gv[y][h] H[h][x],  Gv[y][h] = g(h - y)
-// A wave owns a strip of 16 output columns and walks down it in blocks of
-// 16 rows.  The 16x16 horizontal result sits in the accumulator layout
-// (lane l, element v = row 4*(l/16)+v, column l%16).  That is already a B
-// operand of the vertical product once its contraction index is taken to
-// enumerate those rows; the vertical Toeplitz slices are built for that
-// order, so H never leaves registers.  A ring of DV = ceil((16+2r)/16)
-// horizontal blocks holds what one vertical output block needs.
-//
-// float32 path (16x16x4 f32): channel values are built on the fly from f
-//   in each lane (trig never stored); N, D live in LDS.
-// staged paths (16x16x32 f16 / bf16, f32 accumulation): the workgroup
-//   builds each 16-row block of channels once into LDS in the staging
-//   type (shared by its four strips), horizontal results are rounded to
-//   the staging type for the vertical product; N and D live in LDS.
-// In both, channel f (k = 0) forms a group of its own without trig, and
-// every k >= 1 forms a group of four channels sharing one sin/cos.
+// Single-image launches of the matrix-core filter kernels (the device
+// building blocks, and the description of the method, are in fobf_tiles.h).
 #include <hip/hip_runtime.h>
 
-#include "fobf_internal.h"
+#include <array>
+#include <utility>
+
+#include "fobf_tiles.h"
 
 namespace fobf {
 namespace {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-typedef __bf16 b8 __attribute__((ext_vector_type(8)));
-
-constexpr int MWAVES = 4;             // waves per workgroup = x strips
-constexpr int MTHREADS = 64 * MWAVES;
-constexpr int MSTRIP = 16;            // output columns per wave
-// LDS table (floats): taps g(0..r) at 0, c_k at 64, tap prefix sums at 96;
-// 256 floats keep what follows 16-byte aligned.
-constexpr int LDS_TABLE = 256;
-
-__device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
-  const float t = __builtin_amdgcn_fractf(x);
-  *s = __builtin_amdgcn_sinf(t);
-  *c = __builtin_amdgcn_cosf(t);
-}
-
-__device__ __forceinline__ float tap(const float* gS, int d, int r) {
-  return (d >= -r && d <= r) ? gS[d < 0 ? -d : d] : 0.f;
-}
-
-// in-image tap sum along one axis at coordinate x of an axis of length n
-__device__ __forceinline__ float edge_weight(const float* gsumS, int x, int n, int r) {
-  if (x < 0 || x >= n) return 0.f;
-  const int lo = max(-r, x - n + 1), hi = min(r, x);
-  return gsumS[hi + r + 1] - gsumS[lo + r];
-}
-
-// Scalars of one image, plus the LDS tables (taps g(0..r), c_k, prefix
-// sums of the taps) shared by the workgroup.
-struct Img {
-  const float* __restrict__ in;
-  float* __restrict__ out;
-  int H, W, ld_in, ld_out, r, K;
-  float inv_period;
-};
-
-// Copies the image's tables into LDS.  A macro, not a function: the kernel
-// parameter block must be indexed in the kernel body itself (taking its
-// address for a callee would copy it to scratch memory).
-#define FOBF_LOAD_TABLES(p, tbl)                                              \
-  do {                                                                        \
-    for (int m_ = threadIdx.x; m_ <= (p).r; m_ += blockDim.x) (tbl)[m_] = (p).g[m_];    \
-    for (int k_ = threadIdx.x; k_ < (p).K; k_ += blockDim.x) (tbl)[64 + k_] = (p).c[k_]; \
-    for (int j_ = threadIdx.x; j_ <= 2 * (p).r + 1; j_ += blockDim.x)                   \
-      (tbl)[96 + j_] = (p).gsum[j_];                                          \
-  } while (0)
-
-// =========================================================================
-// float32: 16x16x4 MFMA, channels on the fly, N/D in LDS
-// =========================================================================
-
-// One channel group over this wave's strip: G = 1 is {f} (k = 0, no trig),
-// G = 4 is {C f, S f, C, S} of frequency k >= 1.  Bt / At are the
-// horizontal / vertical Toeplitz slices, one float per lane per MFMA step,
-// precomputed in LDS.  The image values of the next 16-row block are
-// loaded while the current block is on the matrix cores.
-template <int DV, int G>
-__device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
-                                          int nblk, const float* tbl, const float* Bt,
-                                          const float* At, float* Ns, float* Ds, int lane) {
-  const float* cS = tbl + 64;
-  const int r = im.r;
-  const int SH = (MSTRIP + 2 * r + 3) >> 2;   // horizontal 4-column steps
-  const int li = lane & 15;
-  const int lk = lane >> 4;
-  const float kinv = static_cast<float>(k) * im.inv_period;
-  const float ck = cS[k];
-  const int QB = nblk + DV - 1;
-  const int colbase = x0w - r + lk;
-  const int gxo = min(x0w + li, im.W - 1);
-
-  f4 ring[DV][G];
-  float fn[4 * DV];
-  {
-    const int row = y0 - r + li;
-    const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
-#pragma unroll
-    for (int s = 0; s < 4 * DV; ++s) fn[s] = rp[min(max(colbase + 4 * s, 0), im.W - 1)];
-  }
-
-  for (int qq = 0; qq < QB; qq += DV) {
-#pragma unroll
-    for (int u = 0; u < DV; ++u) {
-      const int q = qq + u;
-      if (q < QB) {
-        float fc[4 * DV];
-#pragma unroll
-        for (int s = 0; s < 4 * DV; ++s) fc[s] = fn[s];
-        const int pb = q - (DV - 1);
-        // output-pixel values for this block's fold (issued before the
-        // prefetch so that waiting for them does not wait for it)
-        float fo[4];
-        if (G == 4 && pb >= 0) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int gy = min(y0 + 16 * pb + 4 * lk + v, im.H - 1);
-            fo[v] = im.in[static_cast<size_t>(gy) * im.ld_in + gxo];
-          }
-        }
-        if (q + 1 < QB) {
-          const int row = y0 - r + 16 * (q + 1) + li;
-          const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
-#pragma unroll
-          for (int s = 0; s < 4 * DV; ++s) fn[s] = rp[min(max(colbase + 4 * s, 0), im.W - 1)];
-        }
-        // ---- horizontal pass, H rows 16q .. 16q+15 of the strip ----
-        const int row = y0 - r + 16 * q + li;
-        const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
-        f4 acc[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 4 * DV; ++s) {
-          if (s < SH) {
-            const bool in = rin && static_cast<unsigned>(colbase + 4 * s) <
-                                       static_cast<unsigned>(im.W);
-            const float f = in ? fc[s] : 0.f;
-            const float bh = Bt[s * 64 + lane];
-            float a[G];
-            if (G == 1) {
-              a[0] = f;
-            } else {
-              const float m = in ? 1.f : 0.f;
-              float sn, cs;
-              sincos_rev(kinv * f, &sn, &cs);
-              a[0] = cs * f;
-              a[1] = sn * f;
-              a[2] = cs * m;
-              a[3] = sn * m;
-            }
-#pragma unroll
-            for (int g = 0; g < G; ++g)
-              acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g], bh, acc[g], 0, 0, 0);
-          }
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) ring[u][g] = acc[g];
-
-        // ---- vertical pass, output block pb ----
-        if (pb >= 0) {
-          f4 vacc[G];
-#pragma unroll
-          for (int g = 0; g < G; ++g) vacc[g] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int d = 0; d < DV; ++d) {
-            const int slot = (u + 1 + d) % DV;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const float av = At[(d * 4 + v) * 64 + lane];
-#pragma unroll
-              for (int g = 0; g < G; ++g)
-                vacc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ring[slot][g][v], vacc[g],
-                                                               0, 0, 0);
-            }
-          }
-          // ---- fold into N, D with the output pixel's own trig ----
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int idx = (pb * 4 + v) * 64 + lane;
-            if (G == 1) {
-              Ns[idx] = fmaf(ck, vacc[0][v], Ns[idx]);
-            } else {
-              float sn, cs;
-              sincos_rev(kinv * fo[v], &sn, &cs);
-              Ns[idx] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), Ns[idx]);
-              Ds[idx] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), Ds[idx]);
-            }
-          }
-        }
-      }
-    }
-  }
-}
-
-// Per-lane N and D of the wave's strip live in LDS at ((pb*4 + v)*64 +
-// lane) for output pixel (row 16 pb + 4 (lane/16) + v, column lane % 16):
-// one 16-row block is 256 consecutive floats, so a wave's access is
-// bank-conflict free.
-// N = 0, D = c_0 W(i).
-__device__ __forceinline__ void init_nd(const Img& im, const float* tbl, int x0w, int y0,
-                                        int nblk, float* Ns, float* Ds, int lane) {
-  const float* cS = tbl + 64;
-  const float* sS = tbl + 96;
-  const float wx = edge_weight(sS, x0w + (lane & 15), im.W, im.r);
-  for (int pb = 0; pb < nblk; ++pb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float wy = edge_weight(sS, y0 + 16 * pb + 4 * (lane >> 4) + v, im.H, im.r);
-      const int idx = (pb * 4 + v) * 64 + lane;
-      Ns[idx] = 0.f;
-      Ds[idx] = cS[0] * wx * wy;
-    }
-}
-
-__device__ __forceinline__ void store_nd(const Img& im, int x0w, int y0, int nblk,
-                                         const float* Ns, const float* Ds, int lane,
-                                         float shift = 0.f) {
-  const int gx = x0w + (lane & 15);
-  for (int pb = 0; pb < nblk; ++pb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gy = y0 + 16 * pb + 4 * (lane >> 4) + v;
-      const int idx = (pb * 4 + v) * 64 + lane;
-      if (gy < im.H && gx < im.W)
-        im.out[static_cast<size_t>(gy) * im.ld_out + gx] = Ns[idx] / Ds[idx] + shift;
-    }
-}
-
-// Toeplitz slices as per-lane LDS tables: Bt[s][lane] (horizontal,
-// 4*DV steps) and At[d*4+v][lane] (vertical, DV blocks x 4 rows).
-template <int DV>
-__device__ __forceinline__ void build_f32_tables(const float* gS, int r, float* Bt, float* At) {
-  for (int i = threadIdx.x; i < 4 * DV * 64; i += blockDim.x) {
-    const int s = i >> 6, l = i & 63;
-    Bt[i] = tap(gS, 4 * s + (l >> 4) - r - (l & 15), r);
-    const int d = s >> 2, v = s & 3;
-    At[i] = tap(gS, 16 * d + 4 * (l >> 4) + v - r - (l & 15), r);
-  }
-}
-
-// XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round-robin
-// (block L runs on XCD L % 8); each XCD is given a contiguous run of tiles,
-// walked in panels 8 tiles wide, so the tiles resident on one XCD share
-// their halos in that XCD's L2.  Returns false for padding blocks.
-__device__ __forceinline__ bool tile_of_block(int L, int nblocks, int ntx, int nty, int* tx,
-                                              int* ty) {
-  const int per = nblocks >> 3;
-  const int t = (L & 7) * per + (L >> 3);
-  if (t >= ntx * nty) return false;
-  constexpr int PW = 8;
-  const int panel = t / (PW * nty);
-  const int rem = t - panel * PW * nty;
-  const int pw = min(PW, ntx - panel * PW);
-  *ty = rem / pw;
-  *tx = panel * PW + (rem - *ty * pw);
-  return true;
-}
-
-template <int DV>
-__device__ __forceinline__ void f32_tile(const Img& im, int tx, int ty, int nblk,
-                                         const float* tbl, const float* Bt, const float* At,
-                                         float* nd) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  float* Ns = nd + wave * 2 * nblk * 256;
-  float* Ds = Ns + nblk * 256;
-  const int x0w = tx * (MWAVES * MSTRIP) + wave * MSTRIP;
-  const int y0 = ty * 16 * nblk;
-  init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);
-  f32_group<DV, 1>(im, 0, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
-  for (int k = 1; k < im.K; ++k)
-    f32_group<DV, 4>(im, k, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
-  store_nd(im, x0w, y0, nblk, Ns, Ds, lane);
-}
-
-template <int DV>
-__global__ __launch_bounds__(MTHREADS, (DV <= 5 ? 2 : 1)) void mfma_f32_kernel(ImageParams p,
-                                                                         int nblk) {
+template <int SH>
+__global__ __launch_bounds__(MTHREADS, (SH <= 20 ? 2 : 1)) void mfma_f32_kernel(ImageParams p,
+                                                                          int nblk) {
+  constexpr int DV = (SH + 3) / 4;
   extern __shared__ float lds[];
   const int ntx = (p.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP);
   const int nty = (p.H + 16 * nblk - 1) / (16 * nblk);
@@ -306,263 +25,10 @@ __global__ __launch_bounds__(MTHREADS, (DV <= 5 ? 2 : 1)) void mfma_f32_kernel(I
   float* nd = At + 4 * DV * 64;
   FOBF_LOAD_TABLES(p, tbl);
   __syncthreads();
-  build_f32_tables<DV>(tbl, p.r, Bt, At);
+  build_f32_tables<SH>(tbl, p.r, Bt, At);
   const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
   __syncthreads();
-  f32_tile<DV>(im, tx, ty, nblk, tbl, Bt, At, nd);
-}
-
-// =========================================================================
-// staged fp16 / bf16: 16x16x32 MFMA, channels shared through LDS, N/D in
-// LDS
-// =========================================================================
-
-template <typename OT>
-struct Stage;
-
-template <>
-struct Stage<_Float16> {
-  typedef h8 v8;
-  static constexpr int kParts = 1;        // one fp16 word per staged value
-  __device__ static __forceinline__ f4 mfma(v8 a, v8 b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-  }
-  __device__ static __forceinline__ _Float16 cvt(float x) { return static_cast<_Float16>(x); }
-};
-
-template <>
-struct Stage<__bf16> {
-  typedef b8 v8;
-  // bf16 keeps 8 mantissa bits (relative rounding 2^-9).  The output
-  // divides N by D, and where D/W is small (a pixel unlike most of its
-  // window) that rounding is amplified past half an intensity level.  Every
-  // staged value -- channel, tap and horizontal result -- is therefore held
-  // as hi + lo bf16 words (v = hi + lo, |lo| <= 2^-9 |v|) and each product
-  // is formed as hi*hi + hi*lo + lo*hi, leaving ~2^-16 relative error.
-  static constexpr int kParts = 2;
-  __device__ static __forceinline__ f4 mfma(v8 a, v8 b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-  }
-  __device__ static __forceinline__ __bf16 cvt(float x) { return static_cast<__bf16>(x); }
-};
-
-// LDS pitch (elements) of a staged channel row: >= cw, = 24 (mod 64) so
-// that the 16 rows read by one 16-lane group fall in distinct banks.
-__host__ __device__ constexpr int stage_pitch(int cw) { return ((cw + 39) / 64) * 64 + 24; }
-// staged columns: the window of the last strip ends at 16*(MWAVES-1) + 32*SHS
-__host__ __device__ constexpr int stage_cols(int shs) { return 16 * (MWAVES - 1) + 32 * shs; }
-constexpr int STAGE_CH = 4;   // channels per staged buffer (per word part)
-
-// Builds one 16-row block of G channels (frequency k) into LDS.  Items of 8
-// consecutive columns; element (row, col) of channel g sits at
-// buf[(g * 16 + row) * PC + col], col 0 = image column x0 - r.
-template <typename OT, int G>
-__device__ __forceinline__ void stage_block(const Img& im, float kinv, float shift, int x0,
-                                           int row0, int CW, int PC, OT* buf) {
-  using S = Stage<OT>;
-  typedef typename S::v8 v8;
-  constexpr int NP = S::kParts;
-  const int per_row = CW >> 3;
-  const int items = 16 * per_row;
-  for (int it = threadIdx.x; it < items; it += MTHREADS) {
-    const int rr = it / per_row;
-    const int c8 = (it - rr * per_row) << 3;
-    const int row = row0 + rr;
-    const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
-    const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
-    const int col0 = x0 - im.r + c8;
-    float fv[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) fv[j] = rp[min(max(col0 + j, 0), im.W - 1)];
-    v8 ch[NP][G];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const bool in = rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W);
-      const float f = in ? fv[j] : 0.f;
-      const float fs = in ? fv[j] - shift : 0.f;     // f - m, zero outside
-      float x[G];
-      if (G == 1) {
-        x[0] = fs;
-      } else {
-        const float m = in ? 1.f : 0.f;
-        float sn, cs;
-        sincos_rev(kinv * f, &sn, &cs);
-        x[0] = cs * fs;
-        x[1] = sn * fs;
-        x[2] = cs * m;
-        x[3] = sn * m;
-      }
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        ch[0][g][j] = S::cvt(x[g]);
-        if (NP == 2) ch[NP - 1][g][j] = S::cvt(x[g] - static_cast<float>(ch[0][g][j]));
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < NP; ++h)
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-        *reinterpret_cast<v8*>(buf + ((h * STAGE_CH + g) * 16 + rr) * PC + c8) = ch[h][g];
-  }
-}
-
-template <typename OT, int DV, int G>
-__device__ __forceinline__ void staged_group(const Img& im, int k, float shift, int x0, int y0,
-                                             int nblk, const float* tbl, OT* sbuf, float* Ns,
-                                             float* Ds) {
-  using S = Stage<OT>;
-  typedef typename S::v8 v8;
-  typedef OT o4 __attribute__((ext_vector_type(4)));
-  constexpr int SHS = (DV + 1) / 2;          // 32-column horizontal steps
-  constexpr int NV = (DV + 1) / 2;           // vertical MFMAs (2 blocks each)
-  constexpr int CW = stage_cols(SHS);
-  constexpr int PC = stage_pitch(CW);
-  const float* gS = tbl;
-  const float* cS = tbl + 64;
-  const int r = im.r;
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const float kinv = static_cast<float>(k) * im.inv_period;
-  const float ck = cS[k];
-  const int x0w = x0 + wave * MSTRIP;
-  const int QB = nblk + DV - 1;
-
-  // horizontal weights: lane (lk, n = li), element j <-> column 32s + 8lk + j
-  constexpr int NS = S::kParts;              // words per staged value
-  v8 Bw[SHS][NS];
-#pragma unroll
-  for (int s = 0; s < SHS; ++s)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float w = tap(gS, 32 * s + 8 * lk + j - r - li, r);
-      Bw[s][0][j] = S::cvt(w);
-      if (NS == 2) Bw[s][NS - 1][j] = S::cvt(w - static_cast<float>(Bw[s][0][j]));
-    }
-  // vertical weights: MFMA t pairs H blocks 2t (elements 0..3) and 2t+1
-  // (elements 4..7); element j <-> H row 16 (2t + j/4) + 4 lk + j%4
-  v8 Aw[NV][NS];
-#pragma unroll
-  for (int t = 0; t < NV; ++t)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int blk = 2 * t + (j >> 2);
-      const float w = blk < DV ? tap(gS, 16 * blk + 4 * lk + (j & 3) - r - li, r) : 0.f;
-      Aw[t][0][j] = S::cvt(w);
-      if (NS == 2) Aw[t][NS - 1][j] = S::cvt(w - static_cast<float>(Aw[t][0][j]));
-    }
-
-  o4 ring[DV][NS][G];
-  __syncthreads();   // the previous group's readers are done with both buffers
-  for (int qq = 0; qq < QB; qq += DV) {
-#pragma unroll
-    for (int u = 0; u < DV; ++u) {
-      const int q = qq + u;
-      if (q < QB) {
-        OT* buf = sbuf + (q & 1) * (NS * STAGE_CH * 16 * PC);
-        stage_block<OT, G>(im, kinv, shift, x0, y0 - r + 16 * q, CW, PC, buf);
-        __syncthreads();
-        // ---- horizontal pass of this wave's strip ----
-        f4 acc[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < SHS; ++s)
-#pragma unroll
-          for (int g = 0; g < G; ++g) {
-            v8 a[NS];
-#pragma unroll
-            for (int h = 0; h < NS; ++h)
-              a[h] = *reinterpret_cast<const v8*>(buf + ((h * STAGE_CH + g) * 16 + li) * PC +
-                                                  16 * wave + 32 * s + 8 * lk);
-            // hi*hi (+ lo*hi + hi*lo when values are split)
-#pragma unroll
-            for (int ha = 0; ha < NS; ++ha)
-#pragma unroll
-              for (int hb = 0; hb + ha < NS; ++hb) acc[g] = S::mfma(a[ha], Bw[s][hb], acc[g]);
-          }
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            ring[u][0][g][v] = S::cvt(acc[g][v]);
-            if (NS == 2)
-              ring[u][NS - 1][g][v] = S::cvt(acc[g][v] - static_cast<float>(ring[u][0][g][v]));
-          }
-
-        // ---- vertical pass, output block pb = q - DV + 1 ----
-        const int pb = q - (DV - 1);
-        if (pb >= 0) {
-          f4 vacc[G];
-#pragma unroll
-          for (int g = 0; g < G; ++g) vacc[g] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int t = 0; t < NV; ++t) {
-            const int b0 = 2 * t, b1 = (2 * t + 1 < DV) ? 2 * t + 1 : 2 * t;
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-              v8 b[NS];
-#pragma unroll
-              for (int h = 0; h < NS; ++h) {
-                const o4 e0 = ring[(u + 1 + b0) % DV][h][g];
-                const o4 e1 = ring[(u + 1 + b1) % DV][h][g];
-                b[h] = v8{e0[0], e0[1], e0[2], e0[3], e1[0], e1[1], e1[2], e1[3]};
-              }
-#pragma unroll
-              for (int ha = 0; ha < NS; ++ha)
-#pragma unroll
-                for (int hb = 0; hb + ha < NS; ++hb) vacc[g] = S::mfma(Aw[t][ha], b[hb], vacc[g]);
-            }
-          }
-          const int gx = min(x0w + li, im.W - 1);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int orow = 16 * pb + 4 * lk + v;
-            const int idx = (pb * 4 + v) * 64 + lane;
-            if (G == 1) {
-              Ns[idx] = fmaf(ck, vacc[0][v], Ns[idx]);
-            } else {
-              const int gy = min(y0 + orow, im.H - 1);
-              const float fo = im.in[static_cast<size_t>(gy) * im.ld_in + gx];
-              float sn, cs;
-              sincos_rev(kinv * fo, &sn, &cs);
-              Ns[idx] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), Ns[idx]);
-              Ds[idx] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), Ds[idx]);
-            }
-          }
-        }
-      }
-    }
-  }
-}
-
-template <typename OT, int DV>
-__device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int nblk,
-                                            const float* tbl, OT* sbuf, float* nd) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int TYo = 16 * nblk;
-  float* Ns = nd + wave * 2 * nblk * 256;
-  float* Ds = Ns + nblk * 256;
-  const int x0 = tx * (MWAVES * MSTRIP);
-  const int y0 = ty * TYo;
-  const int x0w = x0 + wave * MSTRIP;
-  // Staged channels carry (f - m) instead of f, m = f at the tile centre:
-  // the numerator becomes N - m D exactly, so out = N'/D + m, and the
-  // magnitudes rounded to the staging type shrink to the local contrast.
-  const float shift = im.in[static_cast<size_t>(min(y0 + TYo / 2, im.H - 1)) * im.ld_in +
-                            min(x0 + MWAVES * MSTRIP / 2, im.W - 1)];
-  init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);
-  staged_group<OT, DV, 1>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
-  for (int k = 1; k < im.K; ++k)
-    staged_group<OT, DV, 4>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
-  store_nd(im, x0w, y0, nblk, Ns, Ds, lane, shift);
-}
-
-template <typename OT, int DV>
-constexpr size_t staged_buf_bytes() {
-  return sizeof(OT) * 2 * Stage<OT>::kParts * STAGE_CH * 16 *
-         stage_pitch(stage_cols((DV + 1) / 2));
+  f32_tile<SH>(im, tx, ty, nblk, tbl, Bt, At, nd);
 }
 
 template <typename OT, int DV>
@@ -602,17 +68,27 @@ fobf_status check_launch(const char* what) {
   return FOBF_OK;
 }
 
-template <int DV>
-fobf_status launch_f32_dv(const ImageParams& p, int nblk, void* stream) {
-  static const bool once = (allow_big_lds(mfma_f32_kernel<DV>), true);
+template <int SH>
+fobf_status launch_f32_sh(const ImageParams& p, int nblk, void* stream) {
+  constexpr int DV = (SH + 3) / 4;
+  static const bool once = (allow_big_lds(mfma_f32_kernel<SH>), true);
   (void)once;
   const size_t lds = sizeof(float) * (LDS_TABLE + 8 * DV * 64 +
                                       static_cast<size_t>(MWAVES) * 2 * nblk * 256);
   dim3 grid(padded_blocks(p, nblk));
-  hipLaunchKernelGGL(mfma_f32_kernel<DV>, grid, dim3(MTHREADS), lds,
+  hipLaunchKernelGGL(mfma_f32_kernel<SH>, grid, dim3(MTHREADS), lds,
                      static_cast<hipStream_t>(stream), p, nblk);
   return check_launch("mfma_f32_kernel");
 }
+
+// dispatch on SH = ceil((16 + 2r) / 4), 5 .. 4 + FOBF_RMAX / 2
+typedef fobf_status (*F32Launcher)(const ImageParams&, int, void*);
+template <int... S>
+constexpr std::array<F32Launcher, sizeof...(S)> f32_table(std::integer_sequence<int, S...>) {
+  return {&launch_f32_sh<S + 5>...};
+}
+constexpr int kMinSH = 5;
+constexpr int kMaxSH = (MSTRIP + 2 * FOBF_RMAX + 3) / 4;
 
 template <typename OT, int DV>
 fobf_status launch_staged_dv(const ImageParams& p, int nblk, void* stream) {
@@ -627,8 +103,7 @@ fobf_status launch_staged_dv(const ImageParams& p, int nblk, void* stream) {
 }
 
 template <typename OT>
-fobf_status launch_staged(const ImageParams& p, int DV, void* stream) {
-  const int nblk = 4;
+fobf_status launch_staged(const ImageParams& p, int DV, int nblk, void* stream) {
   switch (DV) {
     case 2: return launch_staged_dv<OT, 2>(p, nblk, stream);
     case 3: return launch_staged_dv<OT, 3>(p, nblk, stream);
@@ -642,27 +117,18 @@ fobf_status launch_staged(const ImageParams& p, int DV, void* stream) {
 
 }  // namespace
 
-fobf_status launch_mfma(const ImageParams& p, int prec, void* stream) {
+fobf_status launch_mfma(const ImageParams& p, int prec, int nblk, void* stream) {
   const int DV = (MSTRIP + 2 * p.r + 15) / 16;
-  if (prec == FOBF_FP16_STAGE) return launch_staged<_Float16>(p, DV, stream);
-  if (prec == FOBF_BF16_STAGE) return launch_staged<__bf16>(p, DV, stream);
-  const int nblk = 8;
-  switch (DV) {
-    case 2: return launch_f32_dv<2>(p, nblk, stream);
-    case 3: return launch_f32_dv<3>(p, nblk, stream);
-    case 4: return launch_f32_dv<4>(p, nblk, stream);
-    case 5: return launch_f32_dv<5>(p, nblk, stream);
-    case 6: return launch_f32_dv<6>(p, nblk, stream);
-    case 7: return launch_f32_dv<7>(p, nblk, stream);
-    default: return fail(FOBF_EINVAL, "fobf_filter: radius out of range for the MFMA path");
-  }
+  if (nblk < 1 || nblk > 16) return fail(FOBF_EINVAL, "fobf_filter: tile height out of range");
+  if (prec == FOBF_FP16_STAGE) return launch_staged<_Float16>(p, DV, nblk, stream);
+  if (prec == FOBF_BF16_STAGE) return launch_staged<__bf16>(p, DV, nblk, stream);
+  static const auto table = f32_table(std::make_integer_sequence<int, kMaxSH - kMinSH + 1>{});
+  const int SH = (MSTRIP + 2 * p.r + 3) / 4;
+  if (SH < kMinSH || SH > kMaxSH)
+    return fail(FOBF_EINVAL, "fobf_filter: radius out of range for the MFMA path");
+  return table[SH - kMinSH](p, nblk, stream);
 }
 
-int auto_algo(int r, int K, int prec) {
-  (void)r;
-  (void)K;
-  (void)prec;
-  return FOBF_ALGO_MFMA;
-}
+
 
 }  // namespace fobf

@@ -1,0 +1,460 @@
+// Continuous-batching server for the Fourier bilateral filter.
+//
+// submit() may be called from any thread at any time; it validates the
+// request, stamps it and queues it.  One scheduler thread admits queued
+// requests in arrival order while the number in flight and their device
+// bytes (input + output image) fit the configured limits, merges up to
+// max_batch admitted requests into one batch, and issues the batch on the
+// next of a few HIP streams ("lanes"): per request a stream-ordered device
+// allocation and the host-to-device copy, then ONE persistent batched
+// launch for all of them (fobf_filter_batch's kernel), then the copies back
+// and stream-ordered frees.  A host callback at the end of each batch marks
+// its requests done and returns their bytes to the budget, which lets the
+// scheduler admit more: requests that arrive while others are on the
+// device join the next batch as soon as memory frees up, and batches on
+// different lanes overlap (copies of one with the kernel of another).
+//
+// Coefficients are fitted on the host (float64, cached by (R, sigma, K))
+// and each distinct fit is uploaded once into a device-resident table that
+// the batched kernel reads them from.
+//
+// Host image buffers should be pinned (hipHostMalloc, or torch's
+// pin_memory) for the copies to be asynchronous; pageable buffers work but
+// make the scheduler wait for each copy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "fobf_internal.h"
+
+namespace fobf {
+fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t work_bytes,
+                              void* stream, const float* const* c_dev);
+size_t batch_workspace_bytes(int n);
+}  // namespace fobf
+
+using namespace fobf;
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+  uint64_t ticket;
+  fobf_request r;
+  fobf_result res;
+  bool done = false;
+  size_t bytes = 0;
+  float* d_in = nullptr;
+  float* d_out = nullptr;
+  int T = 0;
+  const float* c_dev = nullptr;
+  double c[FOBF_KMAX];
+};
+
+struct Batch;
+
+constexpr int kLanes = 3;
+constexpr int kCoefSlots = 4096;
+
+}  // namespace
+
+struct fobf_server {
+  fobf_serve_cfg cfg{};
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work;
+  std::condition_variable cv_done;
+  std::deque<Req*> pending;
+  std::unordered_map<uint64_t, Req*> reqs;
+  uint64_t next_ticket = 1;
+  size_t bytes_inflight = 0;
+  int n_inflight = 0;
+  int batches_running = 0;
+  bool stop = false;
+  int inject = 0;
+  std::thread worker;
+  hipStream_t lanes[kLanes] = {};
+  int next_lane = 0;
+  // fit cache: (R, sigma bits, K) -> (T, c, device row)
+  struct Coef {
+    int T;
+    double c[FOBF_KMAX];
+    const float* row;
+  };
+  std::map<std::tuple<int, uint64_t, int>, Coef> coef;
+  float* d_coef = nullptr;
+  int coef_used = 0;
+  fobf_serve_stats stats{};
+};
+
+namespace {
+
+struct Batch {
+  fobf_server* s;
+  std::vector<Req*> reqs;
+};
+
+// Runs on a HIP runtime thread when a batch's stream reaches its end: no
+// HIP calls here, only bookkeeping under the server lock.
+void batch_done(void* arg) {
+  Batch* b = static_cast<Batch*>(arg);
+  fobf_server* s = b->s;
+  const double t = now_s();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (Req* q : b->reqs) {
+      q->res.t_done = t;
+      if (q->res.status == FOBF_EBUSY) q->res.status = FOBF_OK;
+      q->done = true;
+      s->bytes_inflight -= q->bytes;
+      s->n_inflight -= 1;
+      s->stats.completed += 1;
+      if (q->res.status != FOBF_OK) s->stats.failed += 1;
+    }
+    s->batches_running -= 1;
+  }
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();
+  delete b;
+}
+
+// Completes requests that never reached the device (caller holds no lock).
+void finish_now(fobf_server* s, const std::vector<Req*>& qs, fobf_status st) {
+  const double t = now_s();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (Req* q : qs) {
+      q->res.status = st;
+      q->res.t_done = t;
+      q->done = true;
+      s->bytes_inflight -= q->bytes;
+      s->n_inflight -= 1;
+      s->stats.completed += 1;
+      s->stats.failed += 1;
+    }
+  }
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();
+}
+
+// Coefficients for (R, sigma, K): host fit on a miss, then one upload of
+// the float32 row into the device table.  Worker thread only.
+fobf_status coefficients(fobf_server* s, Req* q, hipStream_t st) {
+  uint64_t sb;
+  std::memcpy(&sb, &q->r.sigma, sizeof(sb));
+  const auto key = std::make_tuple(s->cfg.R, sb, q->r.K);
+  auto it = s->coef.find(key);
+  if (it == s->coef.end()) {
+    fobf_coef fc;
+    fobf_status st_fit = fobf_fit(s->cfg.R, q->r.sigma, q->r.K, s->cfg.eps, 0, &fc);
+    if (st_fit != FOBF_OK && st_fit != FOBF_WARN_TOL) return st_fit;
+    fobf_server::Coef e{};
+    e.T = fc.T;
+    for (int k = 0; k < q->r.K; ++k) e.c[k] = fc.c[k];
+    e.row = nullptr;
+    if (s->coef_used < kCoefSlots) {
+      float row[FOBF_KMAX];
+      for (int k = 0; k < FOBF_KMAX; ++k) row[k] = k < q->r.K ? static_cast<float>(fc.c[k]) : 0.f;
+      float* dst = s->d_coef + static_cast<size_t>(s->coef_used) * FOBF_KMAX;
+      fobf_status up = upload_async(dst, row, sizeof(row), st);
+      if (up != FOBF_OK) return up;
+      e.row = dst;
+      s->coef_used += 1;
+    }
+    it = s->coef.emplace(key, e).first;
+  }
+  q->T = it->second.T;
+  std::memcpy(q->c, it->second.c, sizeof(q->c));
+  q->c_dev = it->second.row;
+  return FOBF_OK;
+}
+
+void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
+  const int lane = s->next_lane;
+  s->next_lane = (s->next_lane + 1) % kLanes;
+  hipStream_t st = s->lanes[lane];
+  bool inject = false;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->inject > 0) {
+      s->inject -= 1;
+      inject = true;
+    }
+  }
+  if (inject) {
+    set_error("fobf_serve: injected device submission failure");
+    finish_now(s, adm, FOBF_EHIP);
+    return;
+  }
+  const double t0 = now_s();
+  std::vector<Req*> ok;
+  std::vector<Req*> bad;
+  std::vector<fobf_job> jobs;
+  std::vector<const float*> cdev;
+  for (Req* q : adm) {
+    q->res.t_start = t0;
+    fobf_status cs = coefficients(s, q, st);
+    if (cs != FOBF_OK) {
+      q->res.status = cs;
+      bad.push_back(q);
+      continue;
+    }
+    const size_t img = sizeof(float) * static_cast<size_t>(q->r.H) * q->r.W;
+    if (hipMallocAsync(reinterpret_cast<void**>(&q->d_in), img, st) != hipSuccess ||
+        hipMallocAsync(reinterpret_cast<void**>(&q->d_out), img, st) != hipSuccess) {
+      if (q->d_in) hipFreeAsync(q->d_in, st);
+      q->d_in = q->d_out = nullptr;
+      q->res.status = FOBF_ENOMEM;
+      bad.push_back(q);
+      continue;
+    }
+    const size_t row = sizeof(float) * q->r.W;
+    hipMemcpy2DAsync(q->d_in, row, q->r.h_in, sizeof(float) * q->r.ld_in, row, q->r.H,
+                     hipMemcpyHostToDevice, st);
+    fobf_job j{};
+    j.d_in = q->d_in;
+    j.d_out = q->d_out;
+    j.H = q->r.H;
+    j.W = q->r.W;
+    j.ld_in = j.ld_out = q->r.W;
+    j.theta = q->r.theta;
+    j.K = q->r.K;
+    j.T = q->T;
+    j.prec = q->r.prec;
+    for (int k = 0; k < q->r.K; ++k) j.c[k] = q->c[k];
+    jobs.push_back(j);
+    cdev.push_back(q->c_dev);
+    q->res.T = q->T;
+    ok.push_back(q);
+  }
+  for (Req* q : bad) finish_now(s, {q}, q->res.status);
+  if (ok.empty()) return;
+  void* ws = nullptr;
+  const size_t wsb = batch_workspace_bytes(static_cast<int>(jobs.size()));
+  fobf_status st_b = FOBF_OK;
+  if (hipMallocAsync(&ws, wsb, st) != hipSuccess) {
+    st_b = fail(FOBF_ENOMEM, "fobf_serve: workspace allocation failed");
+  } else {
+    st_b = filter_batch_impl(jobs.data(), static_cast<int>(jobs.size()), ws, wsb, st, cdev.data());
+  }
+  for (Req* q : ok) {
+    if (st_b == FOBF_OK) {
+      const size_t row = sizeof(float) * q->r.W;
+      hipMemcpy2DAsync(q->r.h_out, sizeof(float) * q->r.ld_out, q->d_out, row, row, q->r.H,
+                       hipMemcpyDeviceToHost, st);
+    } else {
+      q->res.status = st_b;
+    }
+    hipFreeAsync(q->d_in, st);
+    hipFreeAsync(q->d_out, st);
+  }
+  if (ws) hipFreeAsync(ws, st);
+  Batch* b = new Batch{s, ok};
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->batches_running += 1;
+    s->stats.batches += 1;
+    s->stats.coef_entries = s->coef_used;
+  }
+  if (hipLaunchHostFunc(st, batch_done, b) != hipSuccess) {
+    // no completion callback: wait here, then complete
+    hipStreamSynchronize(st);
+    batch_done(b);
+  }
+}
+
+void worker_main(fobf_server* s) {
+  hipSetDevice(s->device);
+  for (;;) {
+    std::vector<Req*> adm;
+    std::vector<Req*> cancelled;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      auto admissible = [&]() {
+        return !s->pending.empty() && s->n_inflight < s->cfg.max_inflight &&
+               s->bytes_inflight + s->pending.front()->bytes <= s->cfg.hbm_budget_bytes;
+      };
+      s->cv_work.wait(lk, [&]() { return s->stop || admissible(); });
+      if (s->stop) {
+        while (!s->pending.empty()) {
+          cancelled.push_back(s->pending.front());
+          s->pending.pop_front();
+        }
+      } else {
+        while (admissible() && static_cast<int>(adm.size()) < s->cfg.max_batch) {
+          Req* q = s->pending.front();
+          s->pending.pop_front();
+          s->n_inflight += 1;
+          s->bytes_inflight += q->bytes;
+          s->stats.peak_inflight = std::max(s->stats.peak_inflight, s->n_inflight);
+          s->stats.peak_bytes_inflight = std::max(s->stats.peak_bytes_inflight, s->bytes_inflight);
+          q->res.t_admit = now_s();
+          adm.push_back(q);
+        }
+      }
+    }
+    if (!cancelled.empty()) {
+      const double t = now_s();
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (Req* q : cancelled) {
+          q->res.status = FOBF_ECANCELED;
+          q->res.t_done = t;
+          q->done = true;
+        }
+      }
+      s->cv_done.notify_all();
+    }
+    if (!adm.empty()) submit_batch(s, adm);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->stop && s->pending.empty()) break;
+    }
+  }
+  // drain: every batch on the device finishes before the server goes away
+  for (int i = 0; i < kLanes; ++i) hipStreamSynchronize(s->lanes[i]);
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&]() { return s->batches_running == 0; });
+}
+
+}  // namespace
+
+extern "C" fobf_status fobf_serve_create(const fobf_serve_cfg* cfg, fobf_server** out) {
+  if (!cfg || !out) return fail(FOBF_EINVAL, "fobf_serve_create: NULL argument");
+  if (cfg->hbm_budget_bytes == 0 || cfg->max_inflight < 1 || cfg->max_batch < 1 || cfg->R < 1 ||
+      !(cfg->eps > 0.0))
+    return fail(FOBF_EINVAL, "fobf_serve_create: invalid configuration");
+  fobf_server* s = new fobf_server();
+  s->cfg = *cfg;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(FOBF_EHIP, "fobf_serve_create: no HIP device");
+  }
+  for (int i = 0; i < kLanes; ++i) {
+    if (hipStreamCreateWithFlags(&s->lanes[i], hipStreamNonBlocking) != hipSuccess) {
+      for (int j = 0; j < i; ++j) hipStreamDestroy(s->lanes[j]);
+      delete s;
+      return fail(FOBF_EHIP, "fobf_serve_create: stream creation failed");
+    }
+  }
+  if (hipMalloc(&s->d_coef, sizeof(float) * kCoefSlots * FOBF_KMAX) != hipSuccess) {
+    for (int i = 0; i < kLanes; ++i) hipStreamDestroy(s->lanes[i]);
+    delete s;
+    return fail(FOBF_ENOMEM, "fobf_serve_create: coefficient table allocation failed");
+  }
+  // keep freed stream-ordered memory in the pool (resident) between batches
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  s->worker = std::thread(worker_main, s);
+  *out = s;
+  return FOBF_OK;
+}
+
+extern "C" fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req,
+                                         uint64_t* ticket) {
+  if (!s || !req || !ticket) return fail(FOBF_EINVAL, "fobf_serve_submit: NULL argument");
+  if (!req->h_in || !req->h_out || req->H < 1 || req->W < 1)
+    return fail(FOBF_EINVAL, "fobf_serve_submit: bad image");
+  if ((req->ld_in != 0 && req->ld_in < req->W) || (req->ld_out != 0 && req->ld_out < req->W))
+    return fail(FOBF_EINVAL, "fobf_serve_submit: leading dimension below W");
+  const int r = spatial_radius(req->theta);
+  if (r < 1 || r > FOBF_RMAX) return fail(FOBF_EINVAL, "fobf_serve_submit: bad theta");
+  if (!(req->sigma > 0.0) || !std::isfinite(req->sigma))
+    return fail(FOBF_EINVAL, "fobf_serve_submit: bad sigma");
+  if (req->K < 1 || req->K > FOBF_KMAX || req->K > s->cfg.R + 1)
+    return fail(FOBF_EINVAL, "fobf_serve_submit: bad K");
+  if (req->prec < FOBF_FP32 || req->prec > FOBF_BF16_STAGE)
+    return fail(FOBF_EINVAL, "fobf_serve_submit: bad precision");
+  const size_t bytes = 2 * sizeof(float) * static_cast<size_t>(req->H) * req->W;
+  if (bytes > s->cfg.hbm_budget_bytes)
+    return fail(FOBF_ENOMEM, "fobf_serve_submit: request larger than the HBM budget");
+  Req* q = new Req();
+  q->r = *req;
+  if (q->r.ld_in == 0) q->r.ld_in = q->r.W;
+  if (q->r.ld_out == 0) q->r.ld_out = q->r.W;
+  q->bytes = bytes;
+  q->res.status = FOBF_EBUSY;
+  q->res.t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      delete q;
+      return fail(FOBF_ECANCELED, "fobf_serve_submit: server is stopping");
+    }
+    q->ticket = s->next_ticket++;
+    s->stats.submitted += 1;
+    s->reqs[q->ticket] = q;
+    s->pending.push_back(q);
+    *ticket = q->ticket;
+  }
+  s->cv_work.notify_all();
+  return FOBF_OK;
+}
+
+extern "C" fobf_status fobf_serve_poll(fobf_server* s, uint64_t ticket, int wait,
+                                       fobf_result* res) {
+  if (!s) return fail(FOBF_EINVAL, "fobf_serve_poll: NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(FOBF_EINVAL, "fobf_serve_poll: unknown ticket");
+  Req* q = it->second;
+  if (!q->done && wait) s->cv_done.wait(lk, [&]() { return q->done; });
+  if (res) *res = q->res;
+  if (!q->done) return FOBF_EBUSY;
+  const fobf_status st = q->res.status;
+  s->reqs.erase(it);
+  delete q;
+  if (st != FOBF_OK) set_error("fobf_serve_poll: request failed");
+  return st;
+}
+
+extern "C" fobf_status fobf_serve_inject_fault(fobf_server* s, int count) {
+  if (!s || count < 0) return fail(FOBF_EINVAL, "fobf_serve_inject_fault: bad argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->inject = count;
+  return FOBF_OK;
+}
+
+extern "C" fobf_status fobf_serve_get_stats(fobf_server* s, fobf_serve_stats* out) {
+  if (!s || !out) return fail(FOBF_EINVAL, "fobf_serve_get_stats: NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  return FOBF_OK;
+}
+
+extern "C" fobf_status fobf_serve_destroy(fobf_server* s) {
+  if (!s) return fail(FOBF_EINVAL, "fobf_serve_destroy: NULL server");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (int i = 0; i < kLanes; ++i) {
+    hipStreamSynchronize(s->lanes[i]);
+    hipStreamDestroy(s->lanes[i]);
+  }
+  hipFree(s->d_coef);
+  for (auto& kv : s->reqs) delete kv.second;
+  delete s;
+  return FOBF_OK;
+}

@@ -31,9 +31,11 @@ _ALGO = {"auto": ALGO_AUTO, "valu": ALGO_VALU, "mfma": ALGO_MFMA}
 
 EXPORTS = [
     "fobf_fit", "fobf_fit_samples", "fobf_filter", "fobf_batch_workspace_size",
-    "fobf_filter_batch", "fobf_serve_create", "fobf_serve_submit",
-    "fobf_serve_poll", "fobf_serve_destroy", "fobf_serve_inject_fault",
-    "fobf_last_error", "fobf_version",
+    "fobf_filter_batch", "fobf_autotune", "fobf_tune_save", "fobf_tune_load",
+    "fobf_tune_reset", "fobf_tune_get", "fobf_serve_create",
+    "fobf_serve_submit", "fobf_serve_poll", "fobf_serve_destroy",
+    "fobf_serve_get_stats", "fobf_serve_inject_fault", "fobf_last_error",
+    "fobf_version",
 ]
 
 
@@ -63,8 +65,16 @@ class _ServeCfg(C.Structure):
 
 class _Request(C.Structure):
     _fields_ = [("h_in", C.c_void_p), ("h_out", C.c_void_p), ("H", C.c_int),
-                ("W", C.c_int), ("theta", C.c_double), ("sigma", C.c_double),
+                ("W", C.c_int), ("ld_in", C.c_int), ("ld_out", C.c_int),
+                ("theta", C.c_double), ("sigma", C.c_double),
                 ("K", C.c_int), ("prec", C.c_int)]
+
+
+class _ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64),
+                ("failed", C.c_uint64), ("batches", C.c_uint64),
+                ("peak_bytes_inflight", C.c_size_t), ("peak_inflight", C.c_int),
+                ("coef_entries", C.c_int)]
 
 
 class _Result(C.Structure):
@@ -102,7 +112,15 @@ def _load():
     bind("fobf_serve_poll", [C.c_void_p, C.c_uint64, C.c_int,
                              C.POINTER(_Result)])
     bind("fobf_serve_destroy", [C.c_void_p])
+    bind("fobf_serve_get_stats", [C.c_void_p, C.POINTER(_ServeStats)])
     bind("fobf_serve_inject_fault", [C.c_void_p, C.c_int])
+    bind("fobf_autotune", [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p])
+    bind("fobf_tune_save", [C.c_char_p])
+    bind("fobf_tune_load", [C.c_char_p])
+    bind("fobf_tune_reset", [])
+    bind("fobf_tune_get", [C.c_int, C.c_double, C.POINTER(C.c_int),
+                           C.POINTER(C.c_int)])
+    bind("fobf_version", [])
     lib.fobf_last_error.restype = C.c_char_p
     lib.fobf_fit.restype = C.c_int
     lib.fobf_fit_samples.restype = C.c_int
@@ -218,14 +236,42 @@ def filter(img, theta: float, K: int, T: int, c, prec="fp32", algo="auto",
     return out
 
 
+def autotune(prec="fp32", H=2048, W=2048, K=8, stream=None):
+    """fobf_autotune: time every tile shape for one precision on the device
+    and record the fastest per radius class (synchronises the stream)."""
+    _check(lib.fobf_autotune(_prec(prec), int(H), int(W), int(K),
+                             _stream_ptr(stream)))
+
+
+def tune_get(prec, theta):
+    a, n = C.c_int(), C.c_int()
+    _check(lib.fobf_tune_get(_prec(prec), float(theta), C.byref(a), C.byref(n)))
+    return a.value, n.value
+
+
+def tune_save(path):
+    _check(lib.fobf_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    _check(lib.fobf_tune_load(str(path).encode()))
+
+
+def tune_reset():
+    _check(lib.fobf_tune_reset())
+
+
 def batch_workspace_size(n: int) -> int:
     return int(lib.fobf_batch_workspace_size(int(n)))
 
 
 def make_job(img, out, theta, K, T, c, prec="fp32") -> _Job:
+    """Describe one batch image.  The job keeps references to ``img`` and
+    ``out`` so that the device memory stays alive while it is in use."""
     _check_image(img, "img")
     _check_image(out, "out")
     j = _Job()
+    j._tensors = (img, out)
     j.d_in = img.data_ptr()
     j.d_out = out.data_ptr()
     j.H, j.W = img.shape
@@ -246,10 +292,14 @@ def filter_batch(jobs, workspace=None, stream=None):
     import torch
     n = len(jobs)
     arr = (_Job * max(1, n))(*jobs)
+    # the ctypes array copies the structs; hold the tensors until the call
+    # has enqueued (the caller keeps the job objects for the device work)
+    keep = [getattr(j, "_tensors", None) for j in jobs]  # noqa: F841
     need = batch_workspace_size(n)
     if workspace is None:
         dev = torch.device("cuda")
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        # torch's caching allocator returns blocks aligned to >= 512 bytes
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
     st = lib.fobf_filter_batch(arr, n, C.c_void_p(workspace.data_ptr()),
                                workspace.numel(), _stream_ptr(stream))
     _check(st)
@@ -270,25 +320,39 @@ class Server:
 
     def submit(self, img: np.ndarray, out: np.ndarray, theta, sigma, K,
                prec="fp32") -> int:
-        if img.dtype != np.float32 or not img.flags.c_contiguous or img.ndim != 2:
-            raise TypeError("img must be a C-contiguous 2-D float32 array")
-        if out.dtype != np.float32 or not out.flags.c_contiguous or out.shape != img.shape:
-            raise TypeError("out must match img (C-contiguous float32)")
+        """Queue one host image (2-D float32 with unit column stride; row
+        pitch free).  Both arrays must stay alive and unchanged until the
+        ticket is polled done; pinned memory makes the copies async."""
+        for a, nm in ((img, "img"), (out, "out")):
+            if a.dtype != np.float32 or a.ndim != 2 or a.strides[1] != 4:
+                raise TypeError(f"{nm} must be 2-D float32 with unit column stride")
+        if out.shape != img.shape:
+            raise TypeError("out must have img's shape")
         req = _Request(img.ctypes.data, out.ctypes.data, img.shape[0],
-                       img.shape[1], float(theta), float(sigma), int(K),
-                       _prec(prec))
+                       img.shape[1], img.strides[0] // 4, out.strides[0] // 4,
+                       float(theta), float(sigma), int(K), _prec(prec))
         t = C.c_uint64()
         _check(lib.fobf_serve_submit(self._h, C.byref(req), C.byref(t)))
         self._keep[t.value] = (img, out)
         return t.value
 
     def poll(self, ticket: int, wait=True):
+        """(status, result) of a ticket: EBUSY while pending, else the
+        request's final status (the ticket is then consumed).  Raises for
+        a ticket this server does not know."""
+        if ticket not in self._keep:
+            raise FobfError(EINVAL, "unknown ticket")
         res = _Result()
         st = lib.fobf_serve_poll(self._h, C.c_uint64(ticket), int(bool(wait)),
                                  C.byref(res))
         if st != EBUSY:
             self._keep.pop(ticket, None)
         return st, res
+
+    def stats(self):
+        st = _ServeStats()
+        _check(lib.fobf_serve_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServeStats._fields_}
 
     def inject_fault(self, count=1):
         _check(lib.fobf_serve_inject_fault(self._h, int(count)))

@@ -1,0 +1,112 @@
+"""Serving benchmark driver: a Poisson request stream through fobf_serve.
+
+Requests follow the C5 workload (see workloads.serve_stream): square images
+with log-uniform area between 128^2 and 4096^2, theta ~ U[2,10],
+sigma = round(U[10,100]), K in {4,6,8}, alternating fp32 / fp16-staged,
+arriving at 200 requests per second.  Request images are windows of one
+pinned 4096^2 pool image (passed with its row pitch, never copied on the
+host); outputs land in a ring of pinned buffers.  Latency is the server's
+own submit-to-done time.
+"""
+from __future__ import annotations
+
+import math
+import threading
+import time
+
+import numpy as np
+
+from . import fobf as F
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def bench_serving(pool_img: np.ndarray, n: int = 600, warmup: int = 60,
+                  rate: float = 200.0, seed: int = 1005, warm_cache: bool = True,
+                  budget_bytes: int = 32 << 30, max_inflight: int = 32,
+                  max_batch: int = 8, ring: int = 40):
+    import torch
+
+    import workloads
+
+    stream = workloads.serve_stream(n=n + warmup, rate=rate, seed=seed)
+    PH, PW = pool_img.shape
+    pool = torch.empty((PH, PW), dtype=torch.float32, pin_memory=True)
+    pool.numpy()[:] = pool_img
+    pool_np = pool.numpy()
+    side = max(min(j.H, PH) for j in stream)
+    outs = [torch.empty((side, side), dtype=torch.float32, pin_memory=True).numpy()
+            for _ in range(ring)]
+    if warm_cache:
+        for key in {(j.sigma, j.K) for j in stream}:
+            F.fit(255, key[0], key[1], eps=0.1)
+    srv = F.Server(hbm_budget_bytes=budget_bytes, max_inflight=max_inflight,
+                   max_batch=max_batch, R=255, eps=0.1)
+    tickets = [None] * len(stream)
+    results = [None] * len(stream)
+    sizes = [0] * len(stream)
+    done_evt = [threading.Event() for _ in stream]
+    t0 = time.monotonic() + 0.05
+    err = []
+
+    def poller():
+        try:
+            for i in range(len(stream)):
+                while tickets[i] is None:
+                    time.sleep(0.0002)
+                st, res = srv.poll(tickets[i], wait=True)
+                results[i] = (st, res.t_submit, res.t_admit, res.t_start, res.t_done)
+                done_evt[i].set()
+        except Exception as e:  # surfaced to the caller
+            err.append(e)
+
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    for i, job in enumerate(stream):
+        if i >= ring:
+            done_evt[i - ring].wait()
+        delay = t0 + job.t_arrival - time.monotonic()
+        if delay > 0:
+            time.sleep(delay)
+        rng = np.random.default_rng([seed, i])
+        h = w = min(job.H, PH)
+        y = int(rng.integers(0, PH - h + 1))
+        x = int(rng.integers(0, PW - w + 1))
+        img = pool_np[y:y + h, x:x + w]
+        out = outs[i % ring][:h, :w]
+        sizes[i] = h * w
+        tickets[i] = srv.submit(img, out, job.theta, job.sigma, job.K,
+                                prec="fp16" if job.prec == 1 else "fp32")
+    th.join()
+    stats = srv.stats()
+    srv.close()
+    if err:
+        raise err[0]
+    timed = range(warmup, len(stream))
+    lat = [(results[i][4] - results[i][1]) * 1e3 for i in timed]
+    bad = [i for i in timed if results[i][0] != 0]
+    t_first = min(results[i][1] for i in timed)
+    t_last = max(results[i][4] for i in timed)
+    mpix = sum(sizes[i] for i in timed) / 1e6
+    queue = [(results[i][2] - results[i][1]) * 1e3 for i in timed]
+    return {
+        "requests": len(lat), "warmup": warmup, "offered_rate_rps": rate,
+        "p50_ms": round(_percentile(lat, 0.50), 3),
+        "p99_ms": round(_percentile(lat, 0.99), 3),
+        "mean_ms": round(sum(lat) / len(lat), 3),
+        "admit_wait_p99_ms": round(_percentile(queue, 0.99), 3),
+        "mpix_s": round(mpix / (t_last - t_first), 1),
+        "achieved_rps": round(len(lat) / (t_last - t_first), 1),
+        "failed": len(bad), "coef_cache": "warm" if warm_cache else "cold",
+        "stats": {k: int(v) for k, v in stats.items()},
+        "config": {"hbm_budget_bytes": budget_bytes, "max_inflight": max_inflight,
+                   "max_batch": max_batch, "mix": "even fp32 / odd fp16-staged",
+                   "host_buffers": "pinned"},
+    }

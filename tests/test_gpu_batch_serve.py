@@ -1,0 +1,266 @@
+"""GPU tests of the batched persistent launch, the autotuner table, and the
+continuous-batching server.  Every result is checked against the single
+image kernel and, on small cases, against the FP64 oracle."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 0.5
+
+
+def dev_img(f):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).cuda()
+
+
+def single(F, img, theta, K, T, c, prec):
+    import torch
+    out = F.filter(img, theta, K, T, c, prec=prec)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def small_batch(n=18, seed=5):
+    """Uneven jobs: sizes 20..300 with random aspect, theta in [0.5, 12]
+    (both radius classes), K in 1..10."""
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for i in range(n):
+        H = int(rng.integers(20, 300))
+        W = int(rng.integers(20, 300))
+        theta = float(rng.uniform(0.5, 12.0))
+        sigma = float(round(rng.uniform(10, 80)))
+        K = int(rng.integers(1, 11))
+        f = workloads.voronoi_image(H, W, max(2, H * W // 500), True, 900 + i)
+        jobs.append((f, theta, sigma, K))
+    return jobs
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_batch_matches_single(prec):
+    import torch
+    import paper_1811_02168_amd as F
+    jobs = small_batch()
+    imgs, outs, descs = [], [], []
+    for f, theta, sigma, K in jobs:
+        coef = F.fit(255, sigma, K, eps=1e9)
+        img = dev_img(f)
+        out = torch.full_like(img, -1.0)
+        imgs.append(img)
+        outs.append(out)
+        descs.append(F.make_job(img, out, theta, K, coef.T, coef.c, prec=prec))
+    F.filter_batch(descs)
+    torch.cuda.synchronize()
+    for (f, theta, sigma, K), img, out in zip(jobs, imgs, outs):
+        coef = F.fit(255, sigma, K, eps=1e9)
+        got = out.cpu().numpy().astype(np.float64)
+        ref1 = single(F, img, theta, K, coef.T, coef.c, prec)
+        d = float(np.max(np.abs(got - ref1)))
+        assert d <= (1e-3 if prec == "fp32" else TOL), (f.shape, theta, K, d)
+    # oracle on the first few (small enough for the FP64 oracle)
+    for (f, theta, sigma, K), out in list(zip(jobs, outs))[:4]:
+        coef = F.fit(255, sigma, K, eps=1e9)
+        ref, num, den = O.fourier_direct(f, theta, K, coef.T, coef.c, return_nd=True)
+        mask = den / O.blur_weight(*f.shape, theta) >= 0.01
+        got = out.cpu().numpy().astype(np.float64)
+        assert float(np.max(np.abs(got - ref)[mask])) <= (0.05 if prec == "fp32" else TOL)
+
+
+def test_batch_mixed_precisions_and_edge_jobs():
+    import torch
+    import paper_1811_02168_amd as F
+    jobs = small_batch(n=9, seed=8)
+    descs, outs, refs = [], [], []     # each job keeps its tensors alive
+    for i, (f, theta, sigma, K) in enumerate(jobs):
+        prec = ["fp32", "fp16", "bf16"][i % 3]
+        coef = F.fit(255, sigma, K, eps=1e9)
+        img = dev_img(f)
+        out = torch.zeros_like(img)
+        descs.append(F.make_job(img, out, theta, K, coef.T, coef.c, prec=prec))
+        outs.append((out, prec))
+        refs.append(single(F, img, theta, K, coef.T, coef.c, prec))
+    # a 1x1 job and a job whose image is narrower than its radius
+    tiny = dev_img(np.array([[77.0]]))
+    tiny_out = torch.zeros_like(tiny)
+    c1 = F.fit(255, 30.0, 4, eps=1e9)
+    descs.append(F.make_job(tiny, tiny_out, 5.0, 4, c1.T, c1.c))
+    F.filter_batch(descs)
+    torch.cuda.synchronize()
+    for (out, prec), ref in zip(outs, refs):
+        d = float(np.max(np.abs(out.cpu().numpy() - ref)))
+        assert d <= (1e-3 if prec == "fp32" else TOL)
+    assert abs(float(tiny_out.cpu().numpy()[0, 0]) - 77.0) < 1e-3
+
+
+def test_batch_c4_workload_sample():
+    """A slice of the 256-image uneven workload (sizes log-uniform 64^2 ..
+    2048^2): every image equals its single-image launch."""
+    import torch
+    import paper_1811_02168_amd as F
+    js = workloads.batch_jobs(n=24)
+    descs, items = [], []
+    for j in js:
+        f = workloads.job_image(j)
+        coef = F.fit(255, j.sigma, j.K, eps=1e9)
+        img = dev_img(f)
+        out = torch.empty_like(img)
+        descs.append(F.make_job(img, out, j.theta, j.K, coef.T, coef.c))
+        items.append((img, out, j, coef))
+    F.filter_batch(descs)
+    torch.cuda.synchronize()
+    for img, out, j, coef in items:
+        ref = single(F, img, j.theta, j.K, coef.T, coef.c, "fp32")
+        assert float(np.max(np.abs(out.cpu().numpy() - ref))) <= 1e-3
+
+
+def test_batch_rejects_bad_calls():
+    import torch
+    import paper_1811_02168_amd as F
+    f = dev_img(np.zeros((8, 8)))
+    o = torch.empty_like(f)
+    j = F.make_job(f, o, 1.0, 2, 5, [1.0, 0.0])
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(F.FobfError):
+        F.filter_batch([j], workspace=small)
+    bad = F.make_job(f, o, 1.0, 2, 5, [1.0, 0.0])
+    bad.K = 0
+    with pytest.raises(F.FobfError):
+        F.filter_batch([j, bad])
+    F.filter_batch([])   # no-op
+
+
+def test_autotune_table_roundtrip(tmp_path):
+    import paper_1811_02168_amd as F
+    F.autotune("fp16", 512, 512, 6)
+    a, nb = F.tune_get("fp16", 10.0)
+    assert a == F.ALGO_MFMA and 1 <= nb <= 16
+    p = tmp_path / "tune.txt"
+    F.tune_save(p)
+    F.tune_reset()
+    F.tune_load(p)
+    assert F.tune_get("fp16", 10.0) == (a, nb)
+    # results are unchanged by the tile shape (fp32 parity still holds)
+    F.autotune("fp32", 512, 512, 8)
+    f = workloads.C3.image()[:300, :300]
+    coef = F.fit(255, 50.0, 8, eps=1e9)
+    got = single(F, dev_img(f), 10.0, 8, coef.T, coef.c, "fp32")
+    ref = O.fourier_direct(f, 10.0, 8, coef.T, coef.c)
+    assert float(np.max(np.abs(got - ref))) <= 0.05
+    F.tune_reset()
+
+
+# ------------------------------------------------------------- serving ---
+
+def serve_requests(n=40, seed=3):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        side = int(np.exp(rng.uniform(np.log(16), np.log(400))))
+        H = side
+        W = int(side * rng.uniform(0.6, 1.6)) + 1
+        f = workloads.voronoi_image(H, W, max(2, H * W // 600), True, 4000 + i)
+        theta = float(rng.uniform(1.0, 10.0))
+        sigma = float(round(rng.uniform(10, 100)))
+        K = int(rng.choice([4, 6, 8]))
+        prec = "fp16" if i % 2 else "fp32"
+        reqs.append((f.astype(np.float32), theta, sigma, K, prec))
+    return reqs
+
+
+def expected(F, f, theta, sigma, K, prec):
+    coef = F.fit(255, sigma, K, eps=0.1)
+    return single(F, dev_img(f), theta, K, coef.T, coef.c, prec)
+
+
+def test_serve_mix_equals_alone():
+    """Each result is the same whether its request ran alone or in the
+    concurrent mix (two submitting threads, small budget forcing
+    admission waits), within the stated tolerance."""
+    import paper_1811_02168_amd as F
+    reqs = serve_requests()
+    budget = 6 * 400 * 700 * 8
+    outs = [np.zeros_like(r[0]) for r in reqs]
+    with F.Server(hbm_budget_bytes=budget, max_inflight=8, max_batch=4) as srv:
+        tickets = [None] * len(reqs)
+
+        def sub(idx):
+            for i in idx:
+                f, theta, sigma, K, prec = reqs[i]
+                tickets[i] = srv.submit(f, outs[i], theta, sigma, K, prec=prec)
+
+        th = [threading.Thread(target=sub, args=(range(k, len(reqs), 2),)) for k in (0, 1)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        for i, t in enumerate(tickets):
+            st, res = srv.poll(t, wait=True)
+            assert st == 0, (i, F.last_error())
+            assert res.t_submit <= res.t_admit <= res.t_start <= res.t_done
+        stats = srv.stats()
+        assert stats["peak_bytes_inflight"] <= budget
+        assert stats["peak_inflight"] <= 8
+        assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    # alone: one request at a time through a fresh server
+    with F.Server(hbm_budget_bytes=budget, max_inflight=1, max_batch=1) as srv:
+        for i, (f, theta, sigma, K, prec) in enumerate(reqs):
+            alone = np.zeros_like(f)
+            st, _ = srv.poll(srv.submit(f, alone, theta, sigma, K, prec=prec), wait=True)
+            assert st == 0
+            tol = 1e-3 if prec == "fp32" else TOL
+            assert float(np.max(np.abs(alone - outs[i]))) <= tol
+            ref = expected(F, f, theta, sigma, K, prec)
+            assert float(np.max(np.abs(outs[i] - ref))) <= tol
+
+
+def test_serve_against_oracle_small():
+    import paper_1811_02168_amd as F
+    f = workloads.C1.image()[:120, :150].astype(np.float32)
+    out = np.zeros_like(f)
+    with F.Server(hbm_budget_bytes=1 << 26) as srv:
+        st, res = srv.poll(srv.submit(f, out, 3.0, 30.0, 4), wait=True)
+    assert st == 0
+    coef = F.fit(255, 30.0, 4, eps=0.1)
+    assert res.T == coef.T
+    ref = O.fourier_direct(f.astype(np.float64), 3.0, 4, coef.T, coef.c)
+    assert float(np.max(np.abs(out - ref))) <= 0.05
+
+
+def test_serve_faults_and_errors():
+    import paper_1811_02168_amd as F
+    f = workloads.C1.image()[:64, :64].astype(np.float32)
+    with F.Server(hbm_budget_bytes=1 << 24, max_inflight=1, max_batch=1) as srv:
+        srv.inject_fault(1)
+        o1, o2 = np.zeros_like(f), np.zeros_like(f)
+        t1 = srv.submit(f, o1, 2.0, 30.0, 4)
+        st1, _ = srv.poll(t1, wait=True)
+        assert st1 == F.fobf.EHIP            # injected failure reported
+        t2 = srv.submit(f, o2, 2.0, 30.0, 4)
+        st2, _ = srv.poll(t2, wait=True)
+        assert st2 == 0                      # and the server keeps serving
+        with pytest.raises(F.FobfError) as e:
+            srv.submit(f, o2, -1.0, 30.0, 4)
+        assert e.value.status == F.fobf.EINVAL
+        big = np.zeros((2048, 2048), dtype=np.float32)
+        with pytest.raises(F.FobfError) as e:
+            srv.submit(big, big.copy(), 2.0, 30.0, 4)
+        assert e.value.status == F.fobf.ENOMEM
+        with pytest.raises(F.FobfError):
+            srv.poll(987654321)
+        assert srv.stats()["failed"] == 1
+
+
+def test_serve_destroy_with_pending():
+    import paper_1811_02168_amd as F
+    f = workloads.C2.image()[:256, :256].astype(np.float32)
+    outs = [np.zeros_like(f) for _ in range(12)]
+    srv = F.Server(hbm_budget_bytes=1 << 22, max_inflight=1, max_batch=1)
+    for o in outs:
+        srv.submit(f, o, 5.0, 30.0, 6)
+    srv.close()                              # must not hang or fault

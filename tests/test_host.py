@@ -137,3 +137,53 @@ def test_radius_rule_matches_oracle():
     import paper_1811_02168_amd as F  # noqa: F401
     for theta in [0.1, 1 / 3, 2.0, 10 / 3, 3.0, 5.0, 10.0, 16.0]:
         assert O.spatial_radius(theta) == math.ceil(3.0 * theta)
+
+
+def test_tune_table_host_side(tmp_path):
+    """The tuning table is host state: defaults, file round trip, reset."""
+    import paper_1811_02168_amd as F
+    F.tune_reset()
+    assert F.tune_get("fp32", 10.0) == (F.ALGO_MFMA, 8)
+    assert F.tune_get("fp16", 10.0) == (F.ALGO_MFMA, 4)
+    p = tmp_path / "t.txt"
+    p.write_text("# fobf tuning table v1: prec dv algo nblk ms\n0 5 1 8 1.5\n1 5 2 2 0.3\n"
+                 "9 9 9 9 9\n")
+    F.tune_load(p)
+    assert F.tune_get("fp32", 10.0) == (F.ALGO_VALU, 8)     # r=30 -> dv=5
+    assert F.tune_get("fp16", 10.0) == (F.ALGO_MFMA, 2)
+    assert F.tune_get("fp32", 2.0) == (F.ALGO_MFMA, 8)      # other dv untouched
+    F.tune_save(tmp_path / "u.txt")
+    assert "0 5 1 8" in (tmp_path / "u.txt").read_text()
+    F.tune_reset()
+    assert F.tune_get("fp32", 10.0) == (F.ALGO_MFMA, 8)
+    (tmp_path / "bad.txt").write_text("garbage\n")
+    with pytest.raises(F.FobfError):
+        F.tune_load(tmp_path / "bad.txt")
+
+
+def test_batch_validation_without_device():
+    import ctypes as C
+    import paper_1811_02168_amd as F
+    assert F.batch_workspace_size(0) >= 256
+    assert F.batch_workspace_size(10) > F.batch_workspace_size(1)
+    assert F.lib.fobf_filter_batch(None, 0, None, 0, None) == 0          # no-op
+    j = F.fobf._Job()
+    j.d_in, j.d_out, j.H, j.W, j.ld_in, j.ld_out = 0x1000, 0x900000, 4, 4, 4, 4
+    j.theta, j.K, j.T, j.prec = 1.0, 0, 5, 0                              # K = 0
+    arr = (F.fobf._Job * 1)(j)
+    st = F.lib.fobf_filter_batch(arr, 1, C.c_void_p(0x100000), 1 << 20, None)
+    assert st == F.fobf.EINVAL and "job 0" in F.last_error()
+    st = F.lib.fobf_filter_batch(arr, 1, C.c_void_p(0x100000), 8, None)
+    assert st == F.fobf.EINVAL                                            # tiny workspace
+
+
+def test_serve_without_device_fails_cleanly():
+    import torch
+    import paper_1811_02168_amd as F
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(F.FobfError) as e:
+        F.Server(hbm_budget_bytes=1 << 20)
+    assert e.value.status in (F.fobf.EHIP, F.fobf.EINVAL)
+    with pytest.raises(F.FobfError):
+        F.Server(hbm_budget_bytes=0)
