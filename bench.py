@@ -73,7 +73,7 @@ def profile_run(modes):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("fobf_mfma.hip", "fobf_api.cpp"):
+    for name in ("fobf_tiles.h", "fobf_mfma.hip", "fobf_api.cpp"):
         with open(os.path.join(ROOT, "paper_1811_02168_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
