@@ -100,13 +100,23 @@ struct Img {
 // One channel group over this wave's strip: G = 1 is {f} (k = 0, no trig),
 // G = 4 is {C f, S f, C, S} of frequency k >= 1.  Bt / At are the
 // horizontal / vertical Toeplitz slices, one float per lane per MFMA step,
-// precomputed in LDS.  The image values of the next 16-row block are
-// loaded while the current block is on the matrix cores.
+// precomputed in LDS.
 //
 // SH = ceil((16 + 2r) / 4) horizontal 4-column steps is a template
 // parameter, so that the step loop has no branches and the compiler can
 // overlap one step's trig with the previous step's matrix work.
-template <int SH, int G>
+//
+// EDGE = false is the interior path: every pixel the strip touches lies in
+// the image, so loads need no clamping (one address per row, immediate
+// offsets) and channels no masks.  On gfx950 the fp32 matrix instruction
+// does not overlap vector-ALU work, so every vector instruction removed
+// from the step loop is time saved.  EDGE = true clamps loads and zeroes
+// the channels of out-of-image neighbours.
+//
+// The image values of the next 16-row block are loaded during the current
+// block's steps: each value is replaced by its successor right after its
+// last use, so the load has a whole block of matrix work to land.
+template <int SH, int G, bool EDGE>
 __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
                                           int nblk, const float* tbl, const float* Bt,
                                           const float* At, float* Ns, float* Ds, int lane) {
@@ -120,64 +130,77 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
   const int QB = nblk + DV - 1;
   const int colbase = x0w - r + lk;
   const int gxo = min(x0w + li, im.W - 1);
+  const size_t ld = static_cast<size_t>(im.ld_in);
+
+  // address of (row y0 - r + 16 q + li, column colbase) -- interior only
+  auto rowptr = [&](int q) { return im.in + (y0 - r + 16 * q + li) * ld + colbase; };
+  auto load_block = [&](int q, float (&v)[SH]) {
+    if (!EDGE) {
+      const float* p = rowptr(q);
+#pragma unroll
+      for (int s = 0; s < SH; ++s) v[s] = p[4 * s];
+    } else {
+      const int row = y0 - r + 16 * q + li;
+      const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * ld;
+#pragma unroll
+      for (int s = 0; s < SH; ++s) v[s] = rp[min(max(colbase + 4 * s, 0), im.W - 1)];
+    }
+  };
 
   f4 ring[DV][G];
-  float fn[SH];
-  {
-    const int row = y0 - r + li;
-    const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
-#pragma unroll
-    for (int s = 0; s < SH; ++s) fn[s] = rp[min(max(colbase + 4 * s, 0), im.W - 1)];
-  }
+  float fv[SH];
+  load_block(0, fv);
 
   for (int qq = 0; qq < QB; qq += DV) {
 #pragma unroll
     for (int u = 0; u < DV; ++u) {
       const int q = qq + u;
       if (q < QB) {
-        float fc[SH];
-#pragma unroll
-        for (int s = 0; s < SH; ++s) fc[s] = fn[s];
         const int pb = q - (DV - 1);
-        // output-pixel values for this block's fold (issued before the
-        // prefetch so that waiting for them does not wait for it)
+        // output-pixel values for this block's fold: issued before this
+        // block's prefetches so that waiting for them waits for nothing else
         float fo[4];
         if (G == 4 && pb >= 0) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int gy = min(y0 + 16 * pb + 4 * lk + v, im.H - 1);
-            fo[v] = im.in[static_cast<size_t>(gy) * im.ld_in + gxo];
+            const int gy = EDGE ? min(y0 + 16 * pb + 4 * lk + v, im.H - 1)
+                                : y0 + 16 * pb + 4 * lk + v;
+            fo[v] = im.in[gy * ld + gxo];
           }
         }
-        if (q + 1 < QB) {
-          const int row = y0 - r + 16 * (q + 1) + li;
-          const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
-#pragma unroll
-          for (int s = 0; s < SH; ++s) fn[s] = rp[min(max(colbase + 4 * s, 0), im.W - 1)];
-        }
+        // next block's row (the last block reloads its own row: branch-free)
+        const int qn = (q + 1 < QB) ? q + 1 : q;
+        const int rown = y0 - r + 16 * qn + li;
+        const float* pn = EDGE ? im.in + static_cast<size_t>(min(max(rown, 0), im.H - 1)) * ld
+                               : rowptr(qn);
         // ---- horizontal pass, H rows 16q .. 16q+15 of the strip ----
         const int row = y0 - r + 16 * q + li;
-        const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
+        const bool rin = !EDGE || static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
         f4 acc[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < SH; ++s) {
-          const bool in = rin && static_cast<unsigned>(colbase + 4 * s) <
-                                     static_cast<unsigned>(im.W);
-          const float f = in ? fc[s] : 0.f;
+          float f = fv[s];
+          float m = 1.f;
+          if (EDGE) {
+            const bool in = rin && static_cast<unsigned>(colbase + 4 * s) <
+                                       static_cast<unsigned>(im.W);
+            f = in ? f : 0.f;
+            m = in ? 1.f : 0.f;
+          }
+          fv[s] = EDGE ? pn[min(max(colbase + 4 * s, 0), im.W - 1)] : pn[4 * s];
           const float bh = Bt[s * 64 + lane];
           float a[G];
           if (G == 1) {
             a[0] = f;
           } else {
-            const float m = in ? 1.f : 0.f;
             float sn, cs;
             sincos_rev(kinv * f, &sn, &cs);
             a[0] = cs * f;
             a[1] = sn * f;
-            a[2] = cs * m;
-            a[3] = sn * m;
+            a[2] = EDGE ? cs * m : cs;
+            a[3] = EDGE ? sn * m : sn;
           }
 #pragma unroll
           for (int g = 0; g < G; ++g)
@@ -220,6 +243,16 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
       }
     }
   }
+}
+
+// True when every pixel a strip's horizontal pass and fold touch lies in
+// the image (no clamping or masking needed).
+template <int SH>
+__device__ __forceinline__ bool strip_interior(const Img& im, int x0w, int y0, int nblk) {
+  constexpr int DV = (SH + 3) / 4;
+  const int r = im.r;
+  return x0w - r >= 0 && x0w - r + 4 * SH <= im.W && y0 - r >= 0 &&
+         y0 - r + 16 * (nblk + DV - 1) <= im.H;
 }
 
 // Per-lane N and D of the wave's strip live in LDS at ((pb*4 + v)*64 +
@@ -298,9 +331,15 @@ __device__ __forceinline__ void f32_tile(const Img& im, int tx, int ty, int nblk
   const int x0w = tx * (MWAVES * MSTRIP) + wave * MSTRIP;
   const int y0 = ty * 16 * nblk;
   init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);
-  f32_group<SH, 1>(im, 0, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
-  for (int k = 1; k < im.K; ++k)
-    f32_group<SH, 4>(im, k, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+  if (strip_interior<SH>(im, x0w, y0, nblk)) {
+    f32_group<SH, 1, false>(im, 0, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+    for (int k = 1; k < im.K; ++k)
+      f32_group<SH, 4, false>(im, k, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+  } else {
+    f32_group<SH, 1, true>(im, 0, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+    for (int k = 1; k < im.K; ++k)
+      f32_group<SH, 4, true>(im, k, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+  }
   store_nd(im, x0w, y0, nblk, Ns, Ds, lane);
 }
 
