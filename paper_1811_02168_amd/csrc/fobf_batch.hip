@@ -103,11 +103,11 @@ __global__ __launch_bounds__(MTHREADS, 1) void batch_kernel(const BatchJob* __re
     } else {
       typedef typename std::conditional<PREC == FOBF_FP16_STAGE, _Float16, __bf16>::type OT;
       OT* sbuf = reinterpret_cast<OT*>(lds + LDS_TABLE);
-      float* nd = lds + LDS_TABLE + staged_buf_bytes<OT, DVHI>() / sizeof(float);
+      float* nd = lds + LDS_TABLE + staged_buf_bytes<OT, DVHI, MWAVES>() / sizeof(float);
       switch (dv) {
 #define FOBF_ST_CASE(D)                                               \
   case D:                                                             \
-    if constexpr (D >= DVLO && D <= DVHI) staged_tile<OT, D>(im, tx, ty, nblk, tbl, sbuf, nd); \
+    if constexpr (D >= DVLO && D <= DVHI) staged_tile<OT, D, MWAVES>(im, tx, ty, nblk, tbl, sbuf, nd); \
     break;
         FOBF_ST_CASE(2)
         FOBF_ST_CASE(3)
@@ -127,8 +127,8 @@ __global__ __launch_bounds__(MTHREADS, 1) void batch_kernel(const BatchJob* __re
 template <int PREC, int DVHI>
 constexpr size_t batch_fixed_lds() {
   if (PREC == FOBF_FP32) return sizeof(float) * (LDS_TABLE + 8 * DVHI * 64);
-  if (PREC == FOBF_FP16_STAGE) return sizeof(float) * LDS_TABLE + staged_buf_bytes<_Float16, DVHI>();
-  return sizeof(float) * LDS_TABLE + staged_buf_bytes<__bf16, DVHI>();
+  if (PREC == FOBF_FP16_STAGE) return sizeof(float) * LDS_TABLE + staged_buf_bytes<_Float16, DVHI, MWAVES>();
+  return sizeof(float) * LDS_TABLE + staged_buf_bytes<__bf16, DVHI, MWAVES>();
 }
 
 // tallest tile (16-row blocks) whose N/D still fits the 160 KB of LDS

@@ -2,6 +2,7 @@
 // building blocks, and the description of the method, are in fobf_tiles.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <utility>
 
@@ -31,20 +32,28 @@ __global__ __launch_bounds__(MTHREADS, (SH <= 20 ? 2 : 1)) void mfma_f32_kernel(
   f32_tile<SH>(im, tx, ty, nblk, tbl, Bt, At, nd);
 }
 
+// Workgroup width of the staged kernels: eight strips for fp16 (wider
+// tiles share more of the horizontal halo's channel work), four for the
+// two-word bf16 staging whose buffers need the LDS.
+template <typename OT>
+constexpr int staged_waves() { return Stage<OT>::kParts == 1 ? 8 : 4; }
+
 template <typename OT, int DV>
-__global__ __launch_bounds__(MTHREADS) void mfma_staged_kernel(ImageParams p, int nblk) {
+__global__ __launch_bounds__(64 * staged_waves<OT>()) void mfma_staged_kernel(ImageParams p,
+                                                                            int nblk) {
+  constexpr int NW = staged_waves<OT>();
   extern __shared__ float lds[];
-  const int ntx = (p.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP);
+  const int ntx = (p.W + NW * MSTRIP - 1) / (NW * MSTRIP);
   const int nty = (p.H + 16 * nblk - 1) / (16 * nblk);
   int tx, ty;
   if (!tile_of_block(blockIdx.x, gridDim.x, ntx, nty, &tx, &ty)) return;
   float* tbl = lds;
   OT* sbuf = reinterpret_cast<OT*>(lds + LDS_TABLE);
-  float* nd = lds + LDS_TABLE + staged_buf_bytes<OT, DV>() / sizeof(float);
+  float* nd = lds + LDS_TABLE + staged_buf_bytes<OT, DV, NW>() / sizeof(float);
   FOBF_LOAD_TABLES(p, tbl);
   const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
   __syncthreads();
-  staged_tile<OT, DV>(im, tx, ty, nblk, tbl, sbuf, nd);
+  staged_tile<OT, DV, NW>(im, tx, ty, nblk, tbl, sbuf, nd);
 }
 
 // ------------------------------------------------------------------ host --
@@ -55,9 +64,9 @@ void allow_big_lds(KernelT kernel) {
                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-// 1-D grid: tiles rounded up to a multiple of the 8 XCDs
-unsigned padded_blocks(const ImageParams& p, int nblk) {
-  const long ntx = (p.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP);
+// 1-D grid: tiles (nw strips wide) rounded up to a multiple of the 8 XCDs
+unsigned padded_blocks(const ImageParams& p, int nblk, int nw = MWAVES) {
+  const long ntx = (p.W + nw * MSTRIP - 1) / (nw * MSTRIP);
   const long nty = (p.H + 16 * nblk - 1) / (16 * nblk);
   return static_cast<unsigned>(((ntx * nty + 7) / 8) * 8);
 }
@@ -94,10 +103,14 @@ template <typename OT, int DV>
 fobf_status launch_staged_dv(const ImageParams& p, int nblk, void* stream) {
   static const bool once = (allow_big_lds(mfma_staged_kernel<OT, DV>), true);
   (void)once;
-  const size_t lds = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV>() +
-                     sizeof(float) * MWAVES * 2 * nblk * 256;
-  dim3 grid(padded_blocks(p, nblk));
-  hipLaunchKernelGGL((mfma_staged_kernel<OT, DV>), grid, dim3(MTHREADS), lds,
+  constexpr int NW = staged_waves<OT>();
+  // the tallest tile whose per-wave N and D still fit next to the staging
+  constexpr size_t fixed = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV, NW>();
+  constexpr int cap = static_cast<int>((160 * 1024 - fixed) / (sizeof(float) * NW * 2 * 256));
+  nblk = std::min(nblk, cap);
+  const size_t lds = fixed + sizeof(float) * NW * 2 * nblk * 256;
+  dim3 grid(padded_blocks(p, nblk, NW));
+  hipLaunchKernelGGL((mfma_staged_kernel<OT, DV>), grid, dim3(64 * NW), lds,
                      static_cast<hipStream_t>(stream), p, nblk);
   return check_launch("mfma_staged_kernel");
 }

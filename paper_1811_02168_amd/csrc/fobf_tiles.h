@@ -381,48 +381,70 @@ struct Stage<__bf16> {
 // LDS pitch (elements) of a staged channel row: >= cw, = 24 (mod 64) so
 // that the 16 rows read by one 16-lane group fall in distinct banks.
 __host__ __device__ constexpr int stage_pitch(int cw) { return ((cw + 39) / 64) * 64 + 24; }
-// staged columns: the window of the last strip ends at 16*(MWAVES-1) + 32*SHS
-__host__ __device__ constexpr int stage_cols(int shs) { return 16 * (MWAVES - 1) + 32 * shs; }
+// staged columns: the window of the last of NW strips ends at
+// 16 (NW - 1) + 32 SHS (columns past 16 NW + 2r only ever meet zero taps)
+__host__ __device__ constexpr int stage_cols(int shs, int nw) { return 16 * (nw - 1) + 32 * shs; }
 constexpr int STAGE_CH = 4;   // channels per staged buffer (per word part)
 
-// Builds one 16-row block of G channels (frequency k) into LDS.  Items of 8
-// consecutive columns; element (row, col) of channel g sits at
-// buf[(g * 16 + row) * PC + col], col 0 = image column x0 - r.
-template <typename OT, int G>
+template <typename OT, int DV, int NW>
+constexpr size_t staged_buf_bytes() {
+  return sizeof(OT) * 2 * Stage<OT>::kParts * STAGE_CH * 16 *
+         stage_pitch(stage_cols((DV + 1) / 2, NW));
+}
+
+// Builds one 16-row block of G channels (frequency k) into LDS for the
+// NW strips of a workgroup.  Only the CWn = 16 NW + 2r columns that meet
+// non-zero taps are computed (the tail stays as zeroed at tile start);
+// items of 8 consecutive columns, one per thread when they fit.  Element
+// (row, col) of channel g, word part h sits at
+// buf[((h * STAGE_CH + g) * 16 + row) * PC + col], col 0 = column x0 - r.
+// `interior`: the block lies inside the image (no clamps or masks).
+template <typename OT, int G, int NW>
 __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shift, int x0,
-                                           int row0, int CW, int PC, OT* buf) {
+                                           int row0, int CWn, int PC, OT* buf, bool interior) {
   using S = Stage<OT>;
   typedef typename S::v8 v8;
   constexpr int NP = S::kParts;
-  const int per_row = CW >> 3;
+  const int per_row = (CWn + 7) >> 3;
   const int items = 16 * per_row;
-  for (int it = threadIdx.x; it < items; it += MTHREADS) {
+  for (int it = threadIdx.x; it < items; it += 64 * NW) {
     const int rr = it / per_row;
     const int c8 = (it - rr * per_row) << 3;
     const int row = row0 + rr;
-    const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
-    const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
     const int col0 = x0 - im.r + c8;
     float fv[8];
+    bool in[8];
+    if (interior) {
+      const float* p = im.in + static_cast<size_t>(row) * im.ld_in + col0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) fv[j] = rp[min(max(col0 + j, 0), im.W - 1)];
+      for (int j = 0; j < 8; ++j) {
+        fv[j] = p[j];
+        in[j] = true;
+      }
+    } else {
+      const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
+      const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        fv[j] = rp[min(max(col0 + j, 0), im.W - 1)];
+        in[j] = rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W);
+      }
+    }
     v8 ch[NP][G];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const bool in = rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W);
-      const float f = in ? fv[j] : 0.f;
-      const float fs = in ? fv[j] - shift : 0.f;     // f - m, zero outside
+      const float f = in[j] ? fv[j] : 0.f;
+      const float fs = in[j] ? fv[j] - shift : 0.f;     // f - m, zero outside
       float x[G];
       if (G == 1) {
         x[0] = fs;
       } else {
-        const float m = in ? 1.f : 0.f;
         float sn, cs;
         sincos_rev(kinv * f, &sn, &cs);
         x[0] = cs * fs;
         x[1] = sn * fs;
-        x[2] = cs * m;
-        x[3] = sn * m;
+        x[2] = in[j] ? cs : 0.f;
+        x[3] = in[j] ? sn : 0.f;
       }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
@@ -438,7 +460,7 @@ __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shi
   }
 }
 
-template <typename OT, int DV, int G>
+template <typename OT, int DV, int G, int NW>
 __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, int x0, int y0,
                                              int nblk, const float* tbl, OT* sbuf, float* Ns,
                                              float* Ds) {
@@ -447,11 +469,12 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   typedef OT o4 __attribute__((ext_vector_type(4)));
   constexpr int SHS = (DV + 1) / 2;          // 32-column horizontal steps
   constexpr int NV = (DV + 1) / 2;           // vertical MFMAs (2 blocks each)
-  constexpr int CW = stage_cols(SHS);
+  constexpr int CW = stage_cols(SHS, NW);
   constexpr int PC = stage_pitch(CW);
   const float* gS = tbl;
   const float* cS = tbl + 64;
   const int r = im.r;
+  const int CWn = 16 * NW + 2 * r;           // columns meeting non-zero taps
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -459,6 +482,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   const float ck = cS[k];
   const int x0w = x0 + wave * MSTRIP;
   const int QB = nblk + DV - 1;
+  const bool cols_in = x0 - r >= 0 && x0 - r + 8 * ((CWn + 7) >> 3) <= im.W;
 
   // horizontal weights: lane (lk, n = li), element j <-> column 32s + 8lk + j
   constexpr int NS = S::kParts;              // words per staged value
@@ -492,7 +516,9 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
       const int q = qq + u;
       if (q < QB) {
         OT* buf = sbuf + (q & 1) * (NS * STAGE_CH * 16 * PC);
-        stage_block<OT, G>(im, kinv, shift, x0, y0 - r + 16 * q, CW, PC, buf);
+        const int row0 = y0 - r + 16 * q;
+        const bool interior = cols_in && row0 >= 0 && row0 + 16 <= im.H;
+        stage_block<OT, G, NW>(im, kinv, shift, x0, row0, CWn, PC, buf, interior);
         __syncthreads();
         // ---- horizontal pass of this wave's strip ----
         f4 acc[G];
@@ -568,7 +594,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   }
 }
 
-template <typename OT, int DV>
+template <typename OT, int DV, int NW>
 __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int nblk,
                                             const float* tbl, OT* sbuf, float* nd) {
   const int wave = threadIdx.x >> 6;
@@ -576,27 +602,27 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
   const int TYo = 16 * nblk;
   float* Ns = nd + wave * 2 * nblk * 256;
   float* Ds = Ns + nblk * 256;
-  const int x0 = tx * (MWAVES * MSTRIP);
+  const int x0 = tx * (NW * MSTRIP);
   const int y0 = ty * TYo;
   const int x0w = x0 + wave * MSTRIP;
+  // zero both staging buffers: the columns past 16 NW + 2r are multiplied
+  // by zero taps and are never written, so they must hold finite values
+  {
+    float4* z = reinterpret_cast<float4*>(sbuf);
+    const int n16 = static_cast<int>(staged_buf_bytes<OT, DV, NW>() / 16);
+    for (int i = threadIdx.x; i < n16; i += 64 * NW) z[i] = float4{0.f, 0.f, 0.f, 0.f};
+  }
   // Staged channels carry (f - m) instead of f, m = f at the tile centre:
   // the numerator becomes N - m D exactly, so out = N'/D + m, and the
   // magnitudes rounded to the staging type shrink to the local contrast.
   const float shift = im.in[static_cast<size_t>(min(y0 + TYo / 2, im.H - 1)) * im.ld_in +
-                            min(x0 + MWAVES * MSTRIP / 2, im.W - 1)];
+                            min(x0 + NW * MSTRIP / 2, im.W - 1)];
   init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);
-  staged_group<OT, DV, 1>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+  staged_group<OT, DV, 1, NW>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
   for (int k = 1; k < im.K; ++k)
-    staged_group<OT, DV, 4>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+    staged_group<OT, DV, 4, NW>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
   store_nd(im, x0w, y0, nblk, Ns, Ds, lane, shift);
 }
-
-template <typename OT, int DV>
-constexpr size_t staged_buf_bytes() {
-  return sizeof(OT) * 2 * Stage<OT>::kParts * STAGE_CH * 16 *
-         stage_pitch(stage_cols((DV + 1) / 2));
-}
-
 
 }  // namespace
 }  // namespace fobf

@@ -34,11 +34,12 @@ std::mutex g_tune_mu;
 Slot g_table[kPrecs][kDvMax + 1];
 
 // Defaults measured on MI355X at 4096^2, r = 30: fp32 8 blocks (2.04 ms vs
-// 2.64 at 4, 2.16 at 16), fp16 4 blocks (1.55 vs 2.04 at 8), bf16 8 blocks
-// (2.25 vs 2.93 at 4).
+// 2.65 at 4, 2.16 at 16), fp16 8 blocks (0.98 ms vs 1.13 at 4), bf16 8
+// blocks (1.84 ms vs 2.34 at 4).  Staged launches cap the height at what
+// fits in LDS.
 TuneChoice builtin(int prec, int dv) {
+  (void)prec;
   (void)dv;
-  if (prec == FOBF_FP16_STAGE) return {FOBF_ALGO_MFMA, 4};
   return {FOBF_ALGO_MFMA, 8};
 }
 

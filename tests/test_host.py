@@ -144,7 +144,7 @@ def test_tune_table_host_side(tmp_path):
     import paper_1811_02168_amd as F
     F.tune_reset()
     assert F.tune_get("fp32", 10.0) == (F.ALGO_MFMA, 8)
-    assert F.tune_get("fp16", 10.0) == (F.ALGO_MFMA, 4)
+    assert F.tune_get("fp16", 10.0) == (F.ALGO_MFMA, 8)
     assert F.tune_get("bf16", 10.0) == (F.ALGO_MFMA, 8)
     p = tmp_path / "t.txt"
     p.write_text("# fobf tuning table v1: prec dv algo nblk ms\n0 5 1 8 1.5\n1 5 2 2 0.3\n"
