@@ -92,6 +92,14 @@ fobf_status fobf_fit(int R, double sigma, int K, double eps, int Tmax,
                      fobf_coef* out);
 
 /*
+ * fobf_fit_cache_clear -- drops every cached fobf_fit result and returns how
+ * many there were.  Later fobf_fit calls solve eq. (5) again.  Servers keep
+ * their own device copies of coefficients they already use; those are not
+ * affected.  Thread-safe; never fails.
+ */
+int fobf_fit_cache_clear(void);
+
+/*
  * fobf_fit_samples -- the same fit for an arbitrary even range kernel given
  * by its samples b[t] = phi(t), t = 0..R (host array of R+1 doubles; the
  * kernel must be even, phi(-t) = phi(t)).  The paper notes that the LS

@@ -25,6 +25,7 @@ SOURCES = [
     "fobf_batch.hip",
     "fobf_tune.hip",
     "fobf_serve.cpp",
+    "fobf_peak.hip",
 ]
 
 ARCH = "gfx950"

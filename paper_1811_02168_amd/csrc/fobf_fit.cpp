@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -71,9 +72,19 @@ bool householder_lstsq(int m, int n, double* M, double* y, double* c) {
   return true;
 }
 
-// cos(2 pi * (k t mod P) / P): exact integer reduction of the argument.
-inline double cos_int(long kt, long P) {
-  return std::cos(kTwoPi * static_cast<double>(kt % P) / static_cast<double>(P));
+// cos(2 pi j / P) for j = 0 .. P/2: with the exact integer reduction
+// j = (k t) mod P and the symmetry cos(2 pi (P - j) / P) = cos(2 pi j / P),
+// every entry of the design matrix for period P is one of these.
+void cos_table(long P, std::vector<double>* tab) {
+  tab->resize(static_cast<size_t>(P / 2 + 1));
+  for (long j = 0; j <= P / 2; ++j)
+    (*tab)[j] = std::cos(kTwoPi * static_cast<double>(j) / static_cast<double>(P));
+}
+
+inline double cos_at(const std::vector<double>& tab, long kt, long P) {
+  long j = kt % P;
+  if (j > P / 2) j = P - j;
+  return tab[j];
 }
 
 struct FitOne {
@@ -83,25 +94,35 @@ struct FitOne {
   double c[FOBF_KMAX];
 };
 
-// E(K, T) of eq. (5) for samples b[0..R] of an even kernel.
-FitOne fit_one(int R, const double* b, int K, int T) {
+// E(K, T) of eq. (5) for samples b[0..R] of an even kernel.  `work` is
+// per-thread scratch reused across periods.
+struct FitWork {
+  std::vector<double> tab, A, M, y;
+};
+
+FitOne fit_one(int R, const double* b, int K, int T, FitWork* w) {
   FitOne r{};
   const int m = R + 1;
   const long P = 2L * T + 1;
-  std::vector<double> M(static_cast<size_t>(m) * K), y(m);
-  for (int t = 0; t <= R; ++t) {
-    const double w = (t == 0) ? 1.0 : std::sqrt(2.0);
-    for (int k = 0; k < K; ++k)
-      M[static_cast<size_t>(k) * m + t] = w * cos_int(static_cast<long>(k) * t, P);
-    y[t] = w * b[t];
-  }
-  r.ok = householder_lstsq(m, K, M.data(), y.data(), r.c);
+  cos_table(P, &w->tab);
+  w->A.resize(static_cast<size_t>(m) * K);
+  w->y.resize(m);
+  for (int k = 0; k < K; ++k)
+    for (int t = 0; t <= R; ++t)
+      w->A[static_cast<size_t>(k) * m + t] = cos_at(w->tab, static_cast<long>(k) * t, P);
+  w->M.resize(w->A.size());
+  for (int k = 0; k < K; ++k)
+    for (int t = 0; t <= R; ++t)
+      w->M[static_cast<size_t>(k) * m + t] =
+          (t == 0 ? 1.0 : std::sqrt(2.0)) * w->A[static_cast<size_t>(k) * m + t];
+  for (int t = 0; t <= R; ++t) w->y[t] = (t == 0 ? 1.0 : std::sqrt(2.0)) * b[t];
+  r.ok = householder_lstsq(m, K, w->M.data(), w->y.data(), r.c);
   if (!r.ok) return r;
   // explicit residual of the unfolded system: t = 0 once, t > 0 twice
   double E = 0, dmax = 0;
   for (int t = 0; t <= R; ++t) {
     double s = 0;
-    for (int k = 0; k < K; ++k) s += r.c[k] * cos_int(static_cast<long>(k) * t, P);
+    for (int k = 0; k < K; ++k) s += r.c[k] * w->A[static_cast<size_t>(k) * m + t];
     const double d = s - b[t];
     E += (t == 0 ? 1.0 : 2.0) * d * d;
     dmax = std::max(dmax, std::fabs(d));
@@ -113,15 +134,39 @@ FitOne fit_one(int R, const double* b, int K, int T) {
 
 // Best period for fixed K: T = max(1, K-1) .. Tmax, smallest E, first T on
 // exact ties.  (For T <= K-2 the columns k and 2T+1-k coincide, so those
-// periods are rank deficient and skipped.)
+// periods are rank deficient and skipped.)  The periods are independent
+// least-squares problems: they are split over up to 8 host threads, each
+// keeping its own best, and merged by (E, T) -- the same answer as one
+// ascending pass, whatever the thread count.
 bool scan_T(int R, const double* b, int K, int Tmax, int* Tbest, FitOne* best) {
+  const int T0 = std::max(1, K - 1);
+  const int nT = Tmax - T0 + 1;
+  if (nT < 1) return false;
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nth = std::max(1, std::min({8, static_cast<int>(hw), nT / 32}));
+  std::vector<FitOne> bestv(nth);
+  std::vector<int> Tv(nth, 0);
+  auto run = [&](int id) {
+    FitWork w;
+    for (int T = T0 + id; T <= Tmax; T += nth) {
+      FitOne f = fit_one(R, b, K, T, &w);
+      if (!f.ok) continue;
+      if (Tv[id] == 0 || f.E < bestv[id].E) {
+        bestv[id] = f;
+        Tv[id] = T;
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int id = 1; id < nth; ++id) pool.emplace_back(run, id);
+  run(0);
+  for (auto& th : pool) th.join();
   bool found = false;
-  for (int T = std::max(1, K - 1); T <= Tmax; ++T) {
-    FitOne f = fit_one(R, b, K, T);
-    if (!f.ok) continue;
-    if (!found || f.E < best->E) {
-      *best = f;
-      *Tbest = T;
+  for (int id = 0; id < nth; ++id) {
+    if (Tv[id] == 0) continue;
+    if (!found || bestv[id].E < best->E || (bestv[id].E == best->E && Tv[id] < *Tbest)) {
+      *best = bestv[id];
+      *Tbest = Tv[id];
       found = true;
     }
   }
@@ -221,6 +266,13 @@ extern "C" fobf_status fobf_fit(int R, double sigma, int K, double eps,
     g_cache[key] = *out;
   }
   return st;
+}
+
+extern "C" int fobf_fit_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  const int n = static_cast<int>(g_cache.size());
+  g_cache.clear();
+  return n;
 }
 
 extern "C" fobf_status fobf_fit_samples(int R, const double* b, int K,

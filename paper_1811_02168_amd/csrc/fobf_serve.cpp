@@ -15,8 +15,12 @@
 // different lanes overlap (copies of one with the kernel of another).
 //
 // Coefficients are fitted on the host (float64, cached by (R, sigma, K))
-// and each distinct fit is uploaded once into a device-resident table that
-// the batched kernel reads them from.
+// by a small pool of fit threads, so that a request whose (sigma, K) has not
+// been seen yet never holds up the admission of requests whose
+// coefficients are ready: the scheduler admits, in arrival order, the
+// queued requests whose fit has finished.  Each distinct fit is uploaded
+// once into a device-resident table that the batched kernel reads them
+// from.
 //
 // Host image buffers should be pinned (hipHostMalloc, or torch's
 // pin_memory) for the copies to be asynchronous; pageable buffers work but
@@ -54,8 +58,11 @@ double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+typedef std::tuple<int, uint64_t, int> CoefKey;   // (R, sigma bits, K)
+
 struct Req {
   uint64_t ticket;
+  CoefKey key;
   fobf_request r;
   fobf_result res;
   bool done = false;
@@ -70,6 +77,7 @@ struct Req {
 struct Batch;
 
 constexpr int kLanes = 3;
+constexpr int kFitThreads = 2;
 constexpr int kCoefSlots = 4096;
 
 }  // namespace
@@ -89,15 +97,22 @@ struct fobf_server {
   bool stop = false;
   int inject = 0;
   std::thread worker;
+  std::thread fitters[kFitThreads];
+  std::condition_variable cv_fit;
+  std::deque<CoefKey> fit_queue;
   hipStream_t lanes[kLanes] = {};
   int next_lane = 0;
-  // fit cache: (R, sigma bits, K) -> (T, c, device row)
+  // fit cache: (R, sigma bits, K) -> (state, T, c, device row).  Guarded
+  // by mu; only the scheduler thread uploads rows.
+  enum CoefState { kFitting, kReady, kFailed };
   struct Coef {
+    CoefState state;
+    fobf_status status;
     int T;
     double c[FOBF_KMAX];
     const float* row;
   };
-  std::map<std::tuple<int, uint64_t, int>, Coef> coef;
+  std::map<CoefKey, Coef> coef;
   float* d_coef = nullptr;
   int coef_used = 0;
   fobf_serve_stats stats{};
@@ -153,36 +168,60 @@ void finish_now(fobf_server* s, const std::vector<Req*>& qs, fobf_status st) {
   s->cv_work.notify_all();
 }
 
-// Coefficients for (R, sigma, K): host fit on a miss, then one upload of
-// the float32 row into the device table.  Worker thread only.
+// Coefficients of an admitted request (its fit has finished): the first
+// use of a fit uploads its float32 row into the device table.  Scheduler
+// thread only.
 fobf_status coefficients(fobf_server* s, Req* q, hipStream_t st) {
-  uint64_t sb;
-  std::memcpy(&sb, &q->r.sigma, sizeof(sb));
-  const auto key = std::make_tuple(s->cfg.R, sb, q->r.K);
-  auto it = s->coef.find(key);
-  if (it == s->coef.end()) {
-    fobf_coef fc;
-    fobf_status st_fit = fobf_fit(s->cfg.R, q->r.sigma, q->r.K, s->cfg.eps, 0, &fc);
-    if (st_fit != FOBF_OK && st_fit != FOBF_WARN_TOL) return st_fit;
-    fobf_server::Coef e{};
-    e.T = fc.T;
-    for (int k = 0; k < q->r.K; ++k) e.c[k] = fc.c[k];
-    e.row = nullptr;
-    if (s->coef_used < kCoefSlots) {
-      float row[FOBF_KMAX];
-      for (int k = 0; k < FOBF_KMAX; ++k) row[k] = k < q->r.K ? static_cast<float>(fc.c[k]) : 0.f;
-      float* dst = s->d_coef + static_cast<size_t>(s->coef_used) * FOBF_KMAX;
-      fobf_status up = upload_async(dst, row, sizeof(row), st);
-      if (up != FOBF_OK) return up;
-      e.row = dst;
-      s->coef_used += 1;
-    }
-    it = s->coef.emplace(key, e).first;
+  fobf_server::Coef e;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    e = s->coef.at(q->key);
   }
-  q->T = it->second.T;
-  std::memcpy(q->c, it->second.c, sizeof(q->c));
-  q->c_dev = it->second.row;
+  if (e.state == fobf_server::kFailed) return fail(e.status, "fobf_serve: coefficient fit failed");
+  if (!e.row && s->coef_used < kCoefSlots) {
+    float row[FOBF_KMAX];
+    for (int k = 0; k < FOBF_KMAX; ++k) row[k] = k < q->r.K ? static_cast<float>(e.c[k]) : 0.f;
+    float* dst = s->d_coef + static_cast<size_t>(s->coef_used) * FOBF_KMAX;
+    fobf_status up = upload_async(dst, row, sizeof(row), st);
+    if (up != FOBF_OK) return up;
+    s->coef_used += 1;
+    e.row = dst;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->coef.at(q->key).row = dst;
+  }
+  q->T = e.T;
+  std::memcpy(q->c, e.c, sizeof(q->c));
+  q->c_dev = e.row;
   return FOBF_OK;
+}
+
+// Fit threads: solve queued (R, sigma, K) keys on the host and mark them
+// ready (or failed), then wake the scheduler.
+void fitter_main(fobf_server* s) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_fit.wait(lk, [&]() { return s->stop || !s->fit_queue.empty(); });
+    if (s->stop) return;
+    const CoefKey key = s->fit_queue.front();
+    s->fit_queue.pop_front();
+    lk.unlock();
+    double sigma;
+    const uint64_t sb = std::get<1>(key);
+    std::memcpy(&sigma, &sb, sizeof(sigma));
+    fobf_coef fc;
+    const fobf_status st = fobf_fit(std::get<0>(key), sigma, std::get<2>(key), s->cfg.eps, 0, &fc);
+    lk.lock();
+    fobf_server::Coef& e = s->coef.at(key);
+    if (st == FOBF_OK || st == FOBF_WARN_TOL) {
+      e.state = fobf_server::kReady;
+      e.T = fc.T;
+      for (int k = 0; k < std::get<2>(key); ++k) e.c[k] = fc.c[k];
+    } else {
+      e.state = fobf_server::kFailed;
+      e.status = st;
+    }
+    s->cv_work.notify_all();
+  }
 }
 
 void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
@@ -286,10 +325,18 @@ void worker_main(fobf_server* s) {
     std::vector<Req*> cancelled;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      auto admissible = [&]() {
-        return !s->pending.empty() && s->n_inflight < s->cfg.max_inflight &&
-               s->bytes_inflight + s->pending.front()->bytes <= s->cfg.hbm_budget_bytes;
+      // the first queued request whose fit has finished, if the limits let
+      // it in (requests still waiting for a fit are passed over)
+      auto next_ready = [&]() -> std::deque<Req*>::iterator {
+        if (s->n_inflight >= s->cfg.max_inflight) return s->pending.end();
+        for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+          if (s->coef.at((*it)->key).state == fobf_server::kFitting) continue;
+          if (s->bytes_inflight + (*it)->bytes <= s->cfg.hbm_budget_bytes) return it;
+          return s->pending.end();
+        }
+        return s->pending.end();
       };
+      auto admissible = [&]() { return next_ready() != s->pending.end(); };
       s->cv_work.wait(lk, [&]() { return s->stop || admissible(); });
       if (s->stop) {
         while (!s->pending.empty()) {
@@ -297,9 +344,11 @@ void worker_main(fobf_server* s) {
           s->pending.pop_front();
         }
       } else {
-        while (admissible() && static_cast<int>(adm.size()) < s->cfg.max_batch) {
-          Req* q = s->pending.front();
-          s->pending.pop_front();
+        for (auto it = next_ready(); it != s->pending.end() &&
+                                     static_cast<int>(adm.size()) < s->cfg.max_batch;
+             it = next_ready()) {
+          Req* q = *it;
+          s->pending.erase(it);
           s->n_inflight += 1;
           s->bytes_inflight += q->bytes;
           s->stats.peak_inflight = std::max(s->stats.peak_inflight, s->n_inflight);
@@ -365,6 +414,7 @@ extern "C" fobf_status fobf_serve_create(const fobf_serve_cfg* cfg, fobf_server*
     hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
   }
   s->worker = std::thread(worker_main, s);
+  for (auto& f : s->fitters) f = std::thread(fitter_main, s);
   *out = s;
   return FOBF_OK;
 }
@@ -392,6 +442,9 @@ extern "C" fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req
   if (q->r.ld_in == 0) q->r.ld_in = q->r.W;
   if (q->r.ld_out == 0) q->r.ld_out = q->r.W;
   q->bytes = bytes;
+  uint64_t sb;
+  std::memcpy(&sb, &req->sigma, sizeof(sb));
+  q->key = CoefKey(s->cfg.R, sb, req->K);
   q->res.status = FOBF_EBUSY;
   q->res.t_submit = now_s();
   {
@@ -402,6 +455,13 @@ extern "C" fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req
     }
     q->ticket = s->next_ticket++;
     s->stats.submitted += 1;
+    if (s->coef.find(q->key) == s->coef.end()) {
+      fobf_server::Coef e{};
+      e.state = fobf_server::kFitting;
+      s->coef.emplace(q->key, e);
+      s->fit_queue.push_back(q->key);
+      s->cv_fit.notify_one();
+    }
     s->reqs[q->ticket] = q;
     s->pending.push_back(q);
     *ticket = q->ticket;
@@ -448,7 +508,10 @@ extern "C" fobf_status fobf_serve_destroy(fobf_server* s) {
     s->stop = true;
   }
   s->cv_work.notify_all();
+  s->cv_fit.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  for (auto& f : s->fitters)
+    if (f.joinable()) f.join();
   for (int i = 0; i < kLanes; ++i) {
     hipStreamSynchronize(s->lanes[i]);
     hipStreamDestroy(s->lanes[i]);

@@ -30,12 +30,12 @@ _PREC = {"fp32": FP32, "f32": FP32, "fp16": FP16_STAGE, "f16": FP16_STAGE,
 _ALGO = {"auto": ALGO_AUTO, "valu": ALGO_VALU, "mfma": ALGO_MFMA}
 
 EXPORTS = [
-    "fobf_fit", "fobf_fit_samples", "fobf_filter", "fobf_batch_workspace_size",
+    "fobf_fit", "fobf_fit_cache_clear", "fobf_fit_samples", "fobf_filter", "fobf_batch_workspace_size",
     "fobf_filter_batch", "fobf_autotune", "fobf_tune_save", "fobf_tune_load",
     "fobf_tune_reset", "fobf_tune_get", "fobf_serve_create",
     "fobf_serve_submit", "fobf_serve_poll", "fobf_serve_destroy",
     "fobf_serve_get_stats", "fobf_serve_inject_fault", "fobf_last_error",
-    "fobf_version",
+    "fobf_version", "fobf_peak",
 ]
 
 
@@ -121,6 +121,8 @@ def _load():
     bind("fobf_tune_get", [C.c_int, C.c_double, C.POINTER(C.c_int),
                            C.POINTER(C.c_int)])
     bind("fobf_version", [])
+    bind("fobf_fit_cache_clear", [])
+    bind("fobf_peak", [C.c_int, C.c_void_p, C.POINTER(C.c_double)])
     lib.fobf_last_error.restype = C.c_char_p
     lib.fobf_fit.restype = C.c_int
     lib.fobf_fit_samples.restype = C.c_int
@@ -186,6 +188,22 @@ def fit(R: int, sigma: float, K: int, eps: float = 0.1, Tmax: int = 0) -> Coef:
                       C.byref(out))
     _check(st, (OK, WARN_TOL))
     return Coef._from(out, st)
+
+
+def fit_cache_clear() -> int:
+    """fobf_fit_cache_clear: drop the host fit cache; returns entries dropped."""
+    return int(lib.fobf_fit_cache_clear())
+
+
+PEAK_KINDS = {"valu_fma_f32": 0, "valu_sin_f32": 1, "mfma_f32": 2,
+              "mfma_f16": 3, "mfma_bf16": 4}
+
+
+def peak(kind: str, stream=None) -> float:
+    """fobf_peak: measured rate of one instruction class (1e12 / s)."""
+    out = C.c_double(0.0)
+    _check(lib.fobf_peak(PEAK_KINDS[kind], _stream_ptr(stream), C.byref(out)))
+    return out.value
 
 
 def fit_samples(R: int, b, K: int, eps: float = 0.1, Tmax: int = 0) -> Coef:

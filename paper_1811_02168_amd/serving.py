@@ -47,6 +47,8 @@ def bench_serving(pool_img: np.ndarray, n: int = 600, warmup: int = 60,
     if warm_cache:
         for key in {(j.sigma, j.K) for j in stream}:
             F.fit(255, key[0], key[1], eps=0.1)
+    else:
+        F.fit_cache_clear()      # every first (sigma, K) pays the eq. (5) fit
     srv = F.Server(hbm_budget_bytes=budget_bytes, max_inflight=max_inflight,
                    max_batch=max_batch, R=255, eps=0.1)
     tickets = [None] * len(stream)

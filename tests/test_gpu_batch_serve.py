@@ -264,3 +264,52 @@ def test_serve_destroy_with_pending():
     for o in outs:
         srv.submit(f, o, 5.0, 30.0, 6)
     srv.close()                              # must not hang or fault
+
+
+def test_serve_cold_fits_do_not_block_ready_requests():
+    """With an empty fit cache, a request whose (sigma, K) must first be
+    fitted on the host does not hold up a later request whose coefficients
+    are ready; every result still equals its single-image launch."""
+    import paper_1811_02168_amd as F
+    f = workloads.C1.image()[:96, :112].astype(np.float32)
+    F.fit_cache_clear()
+    F.fit(255, 40.0, 4, eps=0.1)                     # ready key
+    slow = (255, 47.0, 32)                           # K = 32: the slowest fit
+    o_slow, o_fast = np.zeros_like(f), np.zeros_like(f)
+    with F.Server(hbm_budget_bytes=1 << 26, max_inflight=4, max_batch=4) as srv:
+        # warm the server's own table with the ready key
+        st, _ = srv.poll(srv.submit(f, np.zeros_like(f), 2.0, 40.0, 4), wait=True)
+        assert st == 0
+        t1 = srv.submit(f, o_slow, 2.0, slow[1], slow[2])
+        t2 = srv.submit(f, o_fast, 2.0, 40.0, 4)
+        st2, r2 = srv.poll(t2, wait=True)
+        st1, r1 = srv.poll(t1, wait=True)
+    assert st1 == 0 and st2 == 0
+    assert r2.t_admit <= r1.t_admit          # passed over while fitting
+    c_slow = F.fit(255, slow[1], slow[2], eps=0.1)
+    assert r1.T == c_slow.T
+    ref = single(F, dev_img(f), 2.0, slow[2], c_slow.T, c_slow.c, "fp32")
+    assert float(np.max(np.abs(o_slow - ref))) <= 1e-3
+    c4 = F.fit(255, 40.0, 4, eps=0.1)
+    ref = single(F, dev_img(f), 2.0, 4, c4.T, c4.c, "fp32")
+    assert float(np.max(np.abs(o_fast - ref))) <= 1e-3
+
+
+def test_serve_many_cold_keys():
+    """Twenty distinct (sigma, K) keys, none cached: all complete, each with
+    the period the host fit chooses, and equal to the single-image launch."""
+    import paper_1811_02168_amd as F
+    F.fit_cache_clear()
+    f = workloads.C1.image()[:80, :72].astype(np.float32)
+    keys = [(float(s), K) for s in (12, 23, 35, 61, 88) for K in (3, 5, 7, 9)]
+    outs = [np.zeros_like(f) for _ in keys]
+    with F.Server(hbm_budget_bytes=1 << 26, max_inflight=6, max_batch=3) as srv:
+        ts = [srv.submit(f, o, 3.0, s, K) for o, (s, K) in zip(outs, keys)]
+        res = [srv.poll(t, wait=True) for t in ts]
+    img = dev_img(f)
+    for (st, r), o, (s, K) in zip(res, outs, keys):
+        assert st == 0
+        c = F.fit(255, s, K, eps=0.1)
+        assert r.T == c.T
+        ref = single(F, img, 3.0, K, c.T, c.c, "fp32")
+        assert float(np.max(np.abs(o - ref))) <= 1e-3

@@ -14,9 +14,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    src = open(os.path.join(ROOT, "include", "fobf.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fobf_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for h in sorted(os.listdir(inc)):
+        if h.endswith(".h"):
+            src = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, h)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(fobf_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_header_symbols():
@@ -31,6 +35,15 @@ def test_library_exports_header_symbols():
     for n in names:
         assert getattr(lib, n) is not None
     assert F.lib.fobf_version() >= 100
+    assert "fobf_peak" in names and "fobf_fit_cache_clear" in names
+
+
+def test_peak_rejects_bad_arguments():
+    import ctypes as C
+    import paper_1811_02168_amd as F
+    out = C.c_double(0.0)
+    assert F.lib.fobf_peak(9, None, C.byref(out)) == F.fobf.EINVAL
+    assert F.lib.fobf_peak(0, None, None) == F.fobf.EINVAL
 
 
 SIGMAS = [10.0, 20.0, 30.0, 50.0, 80.0, 100.0]
@@ -54,6 +67,15 @@ def test_host_fit_matches_oracle(sigma):
             assert E_at <= 1e-12
         assert got.delta == pytest.approx(
             O.kernel_maxdev(255, sigma, got.c, got.T), rel=1e-6, abs=1e-14)
+
+
+def test_fit_cache_clear():
+    import paper_1811_02168_amd as F
+    a = F.fit(255, 37.0, 5, eps=1e9)
+    assert F.fit_cache_clear() >= 1
+    assert F.fit_cache_clear() == 0
+    b = F.fit(255, 37.0, 5, eps=1e9)       # solved again, same answer
+    assert (a.T, list(a.c)) == (b.T, list(b.c))
 
 
 def test_host_fit_fig1_and_warn():
