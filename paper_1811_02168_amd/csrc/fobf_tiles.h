@@ -113,6 +113,12 @@ struct Img {
 // from the step loop is time saved.  EDGE = true clamps loads and zeroes
 // the channels of out-of-image neighbours.
 //
+// The contraction index of a horizontal step does not have to run over
+// adjacent columns: step s takes column c = SH*kk + s of the strip's window
+// (kk = lane / 16, the MFMA's k index), and the Toeplitz slice Bt is built
+// for that order.  Each lane then reads SH adjacent floats of one row, a
+// few wide loads per block instead of one 4-byte load per step.
+//
 // The image values of the next 16-row block are loaded during the current
 // block's steps: each value is replaced by its successor right after its
 // last use, so the load has a whole block of matrix work to land.
@@ -128,7 +134,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
   const float kinv = static_cast<float>(k) * im.inv_period;
   const float ck = cS[k];
   const int QB = nblk + DV - 1;
-  const int colbase = x0w - r + lk;
+  const int colbase = x0w - r + SH * lk;
   const int gxo = min(x0w + li, im.W - 1);
   const size_t ld = static_cast<size_t>(im.ld_in);
 
@@ -138,12 +144,12 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
     if (!EDGE) {
       const float* p = rowptr(q);
 #pragma unroll
-      for (int s = 0; s < SH; ++s) v[s] = p[4 * s];
+      for (int s = 0; s < SH; ++s) v[s] = p[s];
     } else {
       const int row = y0 - r + 16 * q + li;
       const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * ld;
 #pragma unroll
-      for (int s = 0; s < SH; ++s) v[s] = rp[min(max(colbase + 4 * s, 0), im.W - 1)];
+      for (int s = 0; s < SH; ++s) v[s] = rp[min(max(colbase + s, 0), im.W - 1)];
     }
   };
 
@@ -157,16 +163,18 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
       const int q = qq + u;
       if (q < QB) {
         const int pb = q - (DV - 1);
-        // output-pixel values for this block's fold: issued before this
-        // block's prefetches so that waiting for them waits for nothing else
+        // output-pixel values for this block's fold, issued first so that
+        // they land during the block's matrix work (rows clamped: blocks
+        // with pb < 0 fold nothing); the scheduling group keeps the loads
+        // at the head of the block
         float fo[4];
-        if (G == 4 && pb >= 0) {
+        if (G == 4) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int gy = EDGE ? min(y0 + 16 * pb + 4 * lk + v, im.H - 1)
-                                : y0 + 16 * pb + 4 * lk + v;
+            const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
             fo[v] = im.in[gy * ld + gxo];
           }
+          __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
         }
         // next block's row (the last block reloads its own row: branch-free)
         const int qn = (q + 1 < QB) ? q + 1 : q;
@@ -184,12 +192,12 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
           float f = fv[s];
           float m = 1.f;
           if (EDGE) {
-            const bool in = rin && static_cast<unsigned>(colbase + 4 * s) <
+            const bool in = rin && static_cast<unsigned>(colbase + s) <
                                        static_cast<unsigned>(im.W);
             f = in ? f : 0.f;
             m = in ? 1.f : 0.f;
           }
-          fv[s] = EDGE ? pn[min(max(colbase + 4 * s, 0), im.W - 1)] : pn[4 * s];
+          fv[s] = EDGE ? pn[min(max(colbase + s, 0), im.W - 1)] : pn[s];
           const float bh = Bt[s * 64 + lane];
           float a[G];
           if (G == 1) {
@@ -227,17 +235,31 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
             }
           }
           // ---- fold into N, D with the output pixel's own trig ----
+          // (all reads of N, D first: they may alias the writes, so reads
+          // issued after a write would each wait for the LDS round trip)
+          float* const nrow = Ns + pb * 256 + lane;
+          float* const drow = Ds + pb * 256 + lane;
+          float nv[4], dv[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int idx = (pb * 4 + v) * 64 + lane;
+            nv[v] = nrow[64 * v];
+            if (G == 4) dv[v] = drow[64 * v];
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
             if (G == 1) {
-              Ns[idx] = fmaf(ck, vacc[0][v], Ns[idx]);
+              nv[v] = fmaf(ck, vacc[0][v], nv[v]);
             } else {
               float sn, cs;
               sincos_rev(kinv * fo[v], &sn, &cs);
-              Ns[idx] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), Ns[idx]);
-              Ds[idx] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), Ds[idx]);
+              nv[v] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), nv[v]);
+              dv[v] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), dv[v]);
             }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            nrow[64 * v] = nv[v];
+            if (G == 4) drow[64 * v] = dv[v];
           }
         }
       }
@@ -289,14 +311,16 @@ __device__ __forceinline__ void store_nd(const Img& im, int x0w, int y0, int nbl
     }
 }
 
-// Toeplitz slices as per-lane LDS tables: Bt[s][lane] (horizontal,
-// 4*DV steps) and At[d*4+v][lane] (vertical, DV blocks x 4 rows).
+// Toeplitz slices as per-lane LDS tables: Bt[s][lane] (horizontal step s,
+// window column SH*(lane/16) + s against output column lane%16; 4*DV
+// entries, those beyond SH unused) and At[d*4+v][lane] (vertical, DV blocks
+// x 4 rows).
 template <int SH>
 __device__ __forceinline__ void build_f32_tables(const float* gS, int r, float* Bt, float* At) {
   constexpr int DV = (SH + 3) / 4;
   for (int i = threadIdx.x; i < 4 * DV * 64; i += blockDim.x) {
     const int s = i >> 6, l = i & 63;
-    Bt[i] = tap(gS, 4 * s + (l >> 4) - r - (l & 15), r);
+    Bt[i] = tap(gS, SH * (l >> 4) + s - r - (l & 15), r);
     const int d = s >> 2, v = s & 3;
     At[i] = tap(gS, 16 * d + 4 * (l >> 4) + v - r - (l & 15), r);
   }
@@ -392,49 +416,76 @@ constexpr size_t staged_buf_bytes() {
          stage_pitch(stage_cols((DV + 1) / 2, NW));
 }
 
-// Builds one 16-row block of G channels (frequency k) into LDS for the
-// NW strips of a workgroup.  Only the CWn = 16 NW + 2r columns that meet
-// non-zero taps are computed (the tail stays as zeroed at tile start);
-// items of 8 consecutive columns, one per thread when they fit.  Element
-// (row, col) of channel g, word part h sits at
+// Staging items: 8 consecutive columns of one row of a 16-row block, one
+// per thread while they fit.  Only the CWn = 16 NW + 2r columns that meet
+// non-zero taps are built (the tail stays as zeroed at tile start).  With
+// r <= 8 (DV - 1) there are at most 32 (NW + DV - 1) items, so a thread
+// holds at most SIT of them.
+template <int DV, int NW>
+constexpr int stage_items_per_thread() { return (NW + DV - 1 + 2 * NW - 1) / (2 * NW); }
+
+// Issues the global loads of one block's items into registers.  Called one
+// block ahead of stage_block, so that the loads land during the matrix
+// work of the current block instead of stalling the staging.  Loads are
+// clamped into the image; stage_block zeroes what lies outside.
+template <int NW, int SIT>
+__device__ __forceinline__ void stage_fetch(const Img& im, int x0, int row0, int CWn,
+                                            bool interior, float (&fv)[SIT][8]) {
+  const int per_row = (CWn + 7) >> 3;
+  const int items = 16 * per_row;
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int it = threadIdx.x + i * 64 * NW;
+    if (it < items) {
+      const int rr = it / per_row;
+      const int c8 = (it - rr * per_row) << 3;
+      const int row = row0 + rr;
+      const int col0 = x0 - im.r + c8;
+      if (interior) {
+        const float* p = im.in + static_cast<size_t>(row) * im.ld_in + col0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) fv[i][j] = p[j];
+      } else {
+        const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) fv[i][j] = rp[min(max(col0 + j, 0), im.W - 1)];
+      }
+    }
+  }
+}
+
+// Builds one 16-row block of G channels (frequency k) into LDS for the NW
+// strips of a workgroup from the values stage_fetch loaded.  Element (row,
+// col) of channel g, word part h sits at
 // buf[((h * STAGE_CH + g) * 16 + row) * PC + col], col 0 = column x0 - r.
-// `interior`: the block lies inside the image (no clamps or masks).
-template <typename OT, int G, int NW>
+// `interior`: the block lies inside the image (no masks).
+template <typename OT, int G, int NW, int SIT>
 __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shift, int x0,
-                                           int row0, int CWn, int PC, OT* buf, bool interior) {
+                                           int row0, int CWn, int PC, OT* buf, bool interior,
+                                           const float (&fvs)[SIT][8]) {
   using S = Stage<OT>;
   typedef typename S::v8 v8;
   constexpr int NP = S::kParts;
   const int per_row = (CWn + 7) >> 3;
   const int items = 16 * per_row;
-  for (int it = threadIdx.x; it < items; it += 64 * NW) {
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int it = threadIdx.x + i * 64 * NW;
+    if (it >= items) continue;
     const int rr = it / per_row;
     const int c8 = (it - rr * per_row) << 3;
     const int row = row0 + rr;
     const int col0 = x0 - im.r + c8;
-    float fv[8];
     bool in[8];
-    if (interior) {
-      const float* p = im.in + static_cast<size_t>(row) * im.ld_in + col0;
+    const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        fv[j] = p[j];
-        in[j] = true;
-      }
-    } else {
-      const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
-      const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        fv[j] = rp[min(max(col0 + j, 0), im.W - 1)];
-        in[j] = rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W);
-      }
-    }
+    for (int j = 0; j < 8; ++j)
+      in[j] = interior || (rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W));
     v8 ch[NP][G];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const float f = in[j] ? fv[j] : 0.f;
-      const float fs = in[j] ? fv[j] - shift : 0.f;     // f - m, zero outside
+      const float f = in[j] ? fvs[i][j] : 0.f;
+      const float fs = in[j] ? fvs[i][j] - shift : 0.f;     // f - m, zero outside
       float x[G];
       if (G == 1) {
         x[0] = fs;
@@ -509,6 +560,10 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
     }
 
   o4 ring[DV][NS][G];
+  constexpr int SIT = stage_items_per_thread<DV, NW>();
+  auto block_interior = [&](int row0) { return cols_in && row0 >= 0 && row0 + 16 <= im.H; };
+  float fvs[SIT][8];
+  stage_fetch<NW, SIT>(im, x0, y0 - r, CWn, block_interior(y0 - r), fvs);
   __syncthreads();   // the previous group's readers are done with both buffers
   for (int qq = 0; qq < QB; qq += DV) {
 #pragma unroll
@@ -517,8 +572,24 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
       if (q < QB) {
         OT* buf = sbuf + (q & 1) * (NS * STAGE_CH * 16 * PC);
         const int row0 = y0 - r + 16 * q;
-        const bool interior = cols_in && row0 >= 0 && row0 + 16 <= im.H;
-        stage_block<OT, G, NW>(im, kinv, shift, x0, row0, CWn, PC, buf, interior);
+        const int pb = q - (DV - 1);
+        // output-pixel values for this block's fold, loaded before the
+        // staging so that they arrive during the block's matrix work (rows
+        // clamped: blocks with pb < 0 fold nothing)
+        float fo[4];
+        if (G == 4) {
+          const int gx = min(x0w + li, im.W - 1);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
+            fo[v] = im.in[static_cast<size_t>(gy) * im.ld_in + gx];
+          }
+        }
+        stage_block<OT, G, NW, SIT>(im, kinv, shift, x0, row0, CWn, PC, buf,
+                                    block_interior(row0), fvs);
+        // next block's loads (the last block reloads its own: branch-free)
+        const int rown = y0 - r + 16 * ((q + 1 < QB) ? q + 1 : q);
+        stage_fetch<NW, SIT>(im, x0, rown, CWn, block_interior(rown), fvs);
         __syncthreads();
         // ---- horizontal pass of this wave's strip ----
         f4 acc[G];
@@ -549,7 +620,6 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
           }
 
         // ---- vertical pass, output block pb = q - DV + 1 ----
-        const int pb = q - (DV - 1);
         if (pb >= 0) {
           f4 vacc[G];
 #pragma unroll
@@ -572,21 +642,30 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
                 for (int hb = 0; hb + ha < NS; ++hb) vacc[g] = S::mfma(Aw[t][ha], b[hb], vacc[g]);
             }
           }
-          const int gx = min(x0w + li, im.W - 1);
+          // fold (all reads of N, D before the writes they may alias)
+          float* const nrow = Ns + pb * 256 + lane;
+          float* const drow = Ds + pb * 256 + lane;
+          float nv[4], dv[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int orow = 16 * pb + 4 * lk + v;
-            const int idx = (pb * 4 + v) * 64 + lane;
+            nv[v] = nrow[64 * v];
+            if (G == 4) dv[v] = drow[64 * v];
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
             if (G == 1) {
-              Ns[idx] = fmaf(ck, vacc[0][v], Ns[idx]);
+              nv[v] = fmaf(ck, vacc[0][v], nv[v]);
             } else {
-              const int gy = min(y0 + orow, im.H - 1);
-              const float fo = im.in[static_cast<size_t>(gy) * im.ld_in + gx];
               float sn, cs;
-              sincos_rev(kinv * fo, &sn, &cs);
-              Ns[idx] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), Ns[idx]);
-              Ds[idx] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), Ds[idx]);
+              sincos_rev(kinv * fo[v], &sn, &cs);
+              nv[v] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), nv[v]);
+              dv[v] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), dv[v]);
             }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            nrow[64 * v] = nv[v];
+            if (G == 4) drow[64 * v] = dv[v];
           }
         }
       }
