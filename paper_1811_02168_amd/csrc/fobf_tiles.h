@@ -410,105 +410,107 @@ __host__ __device__ constexpr int stage_pitch(int cw) { return ((cw + 39) / 64) 
 __host__ __device__ constexpr int stage_cols(int shs, int nw) { return 16 * (nw - 1) + 32 * shs; }
 constexpr int STAGE_CH = 4;   // channels per staged buffer (per word part)
 
+// Staging items: IW consecutive columns of one row of a 16-row block, one
+// item per thread.  Only the CWn = 16 NW + 2r columns that meet non-zero
+// taps are built (the tail stays as zeroed at tile start).  With r <= 8 (DV
+// - 1), a block has at most 16 (16 NW + 16 (DV - 1)) such pixels; IW is the
+// smallest even width that spreads them over the 64 NW threads, so that
+// every wave takes an equal share of the staging work.
+template <int DV, int NW>
+constexpr int stage_item_width() { return 2 * ((2 * (NW + DV - 1) + NW - 1) / NW); }
+
+// Staged row width: the columns the horizontal steps read, and those the
+// staging items cover.
+template <int DV, int NW>
+constexpr int stage_width() {
+  return stage_cols((DV + 1) / 2, NW) > 16 * NW + 16 * (DV - 1) + stage_item_width<DV, NW>()
+             ? stage_cols((DV + 1) / 2, NW)
+             : 16 * NW + 16 * (DV - 1) + stage_item_width<DV, NW>();
+}
+
 template <typename OT, int DV, int NW>
 constexpr size_t staged_buf_bytes() {
-  return sizeof(OT) * 2 * Stage<OT>::kParts * STAGE_CH * 16 *
-         stage_pitch(stage_cols((DV + 1) / 2, NW));
+  return sizeof(OT) * 2 * Stage<OT>::kParts * STAGE_CH * 16 * stage_pitch(stage_width<DV, NW>());
 }
 
-// Staging items: 8 consecutive columns of one row of a 16-row block, one
-// per thread while they fit.  Only the CWn = 16 NW + 2r columns that meet
-// non-zero taps are built (the tail stays as zeroed at tile start).  With
-// r <= 8 (DV - 1) there are at most 32 (NW + DV - 1) items, so a thread
-// holds at most SIT of them.
-template <int DV, int NW>
-constexpr int stage_items_per_thread() { return (NW + DV - 1 + 2 * NW - 1) / (2 * NW); }
-
-// Issues the global loads of one block's items into registers.  Called one
-// block ahead of stage_block, so that the loads land during the matrix
-// work of the current block instead of stalling the staging.  Loads are
-// clamped into the image; stage_block zeroes what lies outside.
-template <int NW, int SIT>
+// Issues the global loads of this thread's item of one block into
+// registers.  Called one block ahead of stage_block, so that the loads land
+// during the matrix work of the current block instead of stalling the
+// staging.  Loads are clamped into the image; stage_block zeroes what lies
+// outside.
+template <int IW>
 __device__ __forceinline__ void stage_fetch(const Img& im, int x0, int row0, int CWn,
-                                            bool interior, float (&fv)[SIT][8]) {
-  const int per_row = (CWn + 7) >> 3;
-  const int items = 16 * per_row;
+                                            bool interior, float (&fv)[IW]) {
+  const int per_row = (CWn + IW - 1) / IW;
+  const int it = threadIdx.x;
+  if (it >= 16 * per_row) return;
+  const int rr = it / per_row;
+  const int row = row0 + rr;
+  const int col0 = x0 - im.r + (it - rr * per_row) * IW;
+  if (interior) {
+    const float* p = im.in + static_cast<size_t>(row) * im.ld_in + col0;
 #pragma unroll
-  for (int i = 0; i < SIT; ++i) {
-    const int it = threadIdx.x + i * 64 * NW;
-    if (it < items) {
-      const int rr = it / per_row;
-      const int c8 = (it - rr * per_row) << 3;
-      const int row = row0 + rr;
-      const int col0 = x0 - im.r + c8;
-      if (interior) {
-        const float* p = im.in + static_cast<size_t>(row) * im.ld_in + col0;
+    for (int j = 0; j < IW; ++j) fv[j] = p[j];
+  } else {
+    const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) fv[i][j] = p[j];
-      } else {
-        const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * im.ld_in;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) fv[i][j] = rp[min(max(col0 + j, 0), im.W - 1)];
-      }
-    }
+    for (int j = 0; j < IW; ++j) fv[j] = rp[min(max(col0 + j, 0), im.W - 1)];
   }
 }
 
-// Builds one 16-row block of G channels (frequency k) into LDS for the NW
-// strips of a workgroup from the values stage_fetch loaded.  Element (row,
-// col) of channel g, word part h sits at
-// buf[((h * STAGE_CH + g) * 16 + row) * PC + col], col 0 = column x0 - r.
-// `interior`: the block lies inside the image (no masks).
-template <typename OT, int G, int NW, int SIT>
+// Builds this thread's item of one 16-row block of G channels (frequency
+// k) into LDS from the values stage_fetch loaded.  Element (row, col) of
+// channel g, word part h sits at buf[((h * STAGE_CH + g) * 16 + row) * PC +
+// col], col 0 = column x0 - r.  `interior`: the block's items lie inside
+// the image (no masks).
+template <typename OT, int G, int IW>
 __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shift, int x0,
                                            int row0, int CWn, int PC, OT* buf, bool interior,
-                                           const float (&fvs)[SIT][8]) {
+                                           const float (&fvs)[IW]) {
   using S = Stage<OT>;
-  typedef typename S::v8 v8;
+  typedef OT o2 __attribute__((ext_vector_type(2)));
   constexpr int NP = S::kParts;
-  const int per_row = (CWn + 7) >> 3;
-  const int items = 16 * per_row;
+  const int per_row = (CWn + IW - 1) / IW;
+  const int it = threadIdx.x;
+  if (it >= 16 * per_row) return;
+  const int rr = it / per_row;
+  const int c0 = (it - rr * per_row) * IW;
+  const int row = row0 + rr;
+  const int col0 = x0 - im.r + c0;
+  const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
+  OT ch[NP][G][IW];
 #pragma unroll
-  for (int i = 0; i < SIT; ++i) {
-    const int it = threadIdx.x + i * 64 * NW;
-    if (it >= items) continue;
-    const int rr = it / per_row;
-    const int c8 = (it - rr * per_row) << 3;
-    const int row = row0 + rr;
-    const int col0 = x0 - im.r + c8;
-    bool in[8];
-    const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      in[j] = interior || (rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W));
-    v8 ch[NP][G];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float f = in[j] ? fvs[i][j] : 0.f;
-      const float fs = in[j] ? fvs[i][j] - shift : 0.f;     // f - m, zero outside
-      float x[G];
-      if (G == 1) {
-        x[0] = fs;
-      } else {
-        float sn, cs;
-        sincos_rev(kinv * f, &sn, &cs);
-        x[0] = cs * fs;
-        x[1] = sn * fs;
-        x[2] = in[j] ? cs : 0.f;
-        x[3] = in[j] ? sn : 0.f;
-      }
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        ch[0][g][j] = S::cvt(x[g]);
-        if (NP == 2) ch[NP - 1][g][j] = S::cvt(x[g] - static_cast<float>(ch[0][g][j]));
-      }
+  for (int j = 0; j < IW; ++j) {
+    const bool in =
+        interior || (rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W));
+    const float f = in ? fvs[j] : 0.f;
+    const float fs = in ? fvs[j] - shift : 0.f;     // f - m, zero outside
+    float x[G];
+    if (G == 1) {
+      x[0] = fs;
+    } else {
+      float sn, cs;
+      sincos_rev(kinv * f, &sn, &cs);
+      x[0] = cs * fs;
+      x[1] = sn * fs;
+      x[2] = in ? cs : 0.f;
+      x[3] = in ? sn : 0.f;
     }
 #pragma unroll
-    for (int h = 0; h < NP; ++h)
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-        *reinterpret_cast<v8*>(buf + ((h * STAGE_CH + g) * 16 + rr) * PC + c8) = ch[h][g];
+    for (int g = 0; g < G; ++g) {
+      ch[0][g][j] = S::cvt(x[g]);
+      if (NP == 2) ch[NP - 1][g][j] = S::cvt(x[g] - static_cast<float>(ch[0][g][j]));
+    }
   }
+  // IW is even and c0 a multiple of IW: pairs of words are 4-byte aligned
+#pragma unroll
+  for (int h = 0; h < NP; ++h)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      o2* dst = reinterpret_cast<o2*>(buf + ((h * STAGE_CH + g) * 16 + rr) * PC + c0);
+#pragma unroll
+      for (int j = 0; j < IW / 2; ++j) dst[j] = o2{ch[h][g][2 * j], ch[h][g][2 * j + 1]};
+    }
 }
 
 template <typename OT, int DV, int G, int NW>
@@ -520,8 +522,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   typedef OT o4 __attribute__((ext_vector_type(4)));
   constexpr int SHS = (DV + 1) / 2;          // 32-column horizontal steps
   constexpr int NV = (DV + 1) / 2;           // vertical MFMAs (2 blocks each)
-  constexpr int CW = stage_cols(SHS, NW);
-  constexpr int PC = stage_pitch(CW);
+  constexpr int PC = stage_pitch(stage_width<DV, NW>());
   const float* gS = tbl;
   const float* cS = tbl + 64;
   const int r = im.r;
@@ -533,7 +534,9 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   const float ck = cS[k];
   const int x0w = x0 + wave * MSTRIP;
   const int QB = nblk + DV - 1;
-  const bool cols_in = x0 - r >= 0 && x0 - r + 8 * ((CWn + 7) >> 3) <= im.W;
+  constexpr int IW = stage_item_width<DV, NW>();
+  static_assert(16 * NW + 16 * (DV - 1) + IW - 1 <= PC, "staged items overrun the pitch");
+  const bool cols_in = x0 - r >= 0 && x0 - r + IW * ((CWn + IW - 1) / IW) <= im.W;
 
   // horizontal weights: lane (lk, n = li), element j <-> column 32s + 8lk + j
   constexpr int NS = S::kParts;              // words per staged value
@@ -560,10 +563,9 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
     }
 
   o4 ring[DV][NS][G];
-  constexpr int SIT = stage_items_per_thread<DV, NW>();
   auto block_interior = [&](int row0) { return cols_in && row0 >= 0 && row0 + 16 <= im.H; };
-  float fvs[SIT][8];
-  stage_fetch<NW, SIT>(im, x0, y0 - r, CWn, block_interior(y0 - r), fvs);
+  float fvs[IW];
+  stage_fetch<IW>(im, x0, y0 - r, CWn, block_interior(y0 - r), fvs);
   __syncthreads();   // the previous group's readers are done with both buffers
   for (int qq = 0; qq < QB; qq += DV) {
 #pragma unroll
@@ -585,11 +587,11 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
             fo[v] = im.in[static_cast<size_t>(gy) * im.ld_in + gx];
           }
         }
-        stage_block<OT, G, NW, SIT>(im, kinv, shift, x0, row0, CWn, PC, buf,
-                                    block_interior(row0), fvs);
+        stage_block<OT, G, IW>(im, kinv, shift, x0, row0, CWn, PC, buf, block_interior(row0),
+                               fvs);
         // next block's loads (the last block reloads its own: branch-free)
         const int rown = y0 - r + 16 * ((q + 1 < QB) ? q + 1 : q);
-        stage_fetch<NW, SIT>(im, x0, rown, CWn, block_interior(rown), fvs);
+        stage_fetch<IW>(im, x0, rown, CWn, block_interior(rown), fvs);
         __syncthreads();
         // ---- horizontal pass of this wave's strip ----
         f4 acc[G];
