@@ -47,7 +47,59 @@ def parse():
                     help="for rocprofv3 counter passes: one 256 MiB device "
                     "copy (calibrates FETCH_SIZE/WRITE_SIZE), then one launch "
                     "per precision of the C3 filter at sigma=50, then exit")
+    ap.add_argument("--write-traffic", metavar="DIR",
+                    help="turn the FETCH_SIZE / WRITE_SIZE counter passes of "
+                    "--profile-run under DIR (DIR/FETCH_SIZE/*.csv, "
+                    "DIR/WRITE_SIZE/*.csv) into profiles/traffic.json, then exit")
+    ap.add_argument("--write-trace-summary", nargs=2, metavar=("STATS_CSV", "BENCH_JSON"),
+                    help="turn a rocprofv3 --kernel-trace --stats summary of a "
+                    "bench run (and that run's JSON line) into "
+                    "profiles/fobf_c3_kernel_trace.md, then exit")
     return ap.parse_args()
+
+
+KERNEL_LABELS = {
+    "mfma_f32_kernel_c3": "fp32 (16x16x4 f32 matrix instruction, 19 horizontal steps = r 30)",
+    "mfma_staged_f16_c3": "fp16-staged (16x16x32 f16, fp32 accumulation)",
+    "mfma_staged_bf16_c3": "bf16 hi+lo staged (16x16x32 bf16, fp32 accumulation)",
+}
+
+
+def write_trace_summary(stats_csv, bench_json):
+    """profiles/fobf_c3_kernel_trace.md from `rocprofv3 --kernel-trace --stats`
+    of `bench.py --no-cpu-baseline --no-serve --no-batch`: per filter kernel,
+    calls and durations, and the flop rate they imply."""
+    import csv
+    line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    flop = line["roofline"]["flop_per_px"] * line["config"]["H"] * line["config"]["W"]
+    rows = list(csv.DictReader(open(stats_csv)))
+    out = ["# Kernel trace: 4096^2 image, theta = 10 (61 taps), K = 8, "
+           "sigma in {20, 50, 100}", "",
+           "Command (from the repository root on the GPU box; "
+           "`cd /tmp && export TMPDIR=/tmp` first):", "",
+           "    rocprofv3 --kernel-trace --stats -d <out>/trace -o fobf "
+           "--output-format csv -- \\",
+           f"        python3 bench.py --steps {line['steps']} --warmup {line['warmup']} "
+           "--no-cpu-baseline --no-serve --no-batch", "",
+           "Summary written by `python3 bench.py --write-trace-summary "
+           "<out>/trace/fobf_kernel_stats.csv <bench JSON line>`.", "",
+           "| Kernel | Calls | Average ns | Min ns | Max ns | TFLOP/s (7076 flop/px) "
+           "| fraction of 157.3 |", "|---|---|---|---|---|---|---|"]
+    for key, subs in TRAFFIC_KERNELS.items():
+        for r in rows:
+            if any(x in r["Name"] for x in subs):
+                avg = float(r["AverageNs"])
+                tf = flop / (avg * 1e-9) / 1e12
+                out.append(f"| `{r['Name'][:90]}` {KERNEL_LABELS[key]} | {r['Calls']} | "
+                           f"{avg:,.0f} | {int(float(r['MinNs'])):,} | "
+                           f"{int(float(r['MaxNs'])):,} | {tf:.1f} | "
+                           f"{tf / PEAK_FP32_TFLOPS:.3f} |")
+    out += ["", "The same run's own HIP-event timing (`roofline.kernel_ms`, "
+            f"uninstrumented): fp32 {line['roofline']['kernel_ms']} ms per launch; "
+            + ", ".join(f"{k} {v['kernel_ms']} ms" for k, v in line.get("mixed", {}).items())
+            + ".", ""]
+    with open(os.path.join(ROOT, "profiles", "fobf_c3_kernel_trace.md"), "w") as fh:
+        fh.write("\n".join(out))
 
 
 def profile_run(modes):
@@ -81,6 +133,80 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+TRAFFIC_KERNELS = {            # key -> substrings naming the kernel
+    "mfma_f32_kernel_c3": ("mfma_f32_kernel<19>", "mfma_f32_kernelILi19E"),
+    "mfma_staged_f16_c3": ("mfma_staged_kernel<_Float16, 5>", "mfma_staged_kernelIDF16_Li5E"),
+    "mfma_staged_bf16_c3": ("mfma_staged_kernel<__bf16, 5>", "mfma_staged_kernelIDF16bLi5E"),
+}
+
+
+def write_traffic(d):
+    """profiles/traffic.json from two rocprofv3 --pmc passes of
+    `bench.py --profile-run`: per kernel, FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) scaled by the factor that makes each counter read 256 MiB for
+    the 256 MiB device-to-device copy of the same run."""
+    import csv
+    import glob
+
+    def rows(counter):
+        files = glob.glob(os.path.join(d, counter, "*counter_collection.csv"))
+        if not files:
+            raise SystemExit(f"no {counter} counter CSV under {d}")
+        per = {}
+        for r in csv.DictReader(open(files[0])):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        return per
+
+    fetch, write = rows("FETCH_SIZE"), rows("WRITE_SIZE")
+    copy_kib = 256 * 1024.0
+
+    def copy_read(per):
+        vals = [v for (_, name), v in per.items() if "copyBuffer" in name]
+        if not vals:
+            raise SystemExit("the calibration copy is missing from the counter pass")
+        return max(vals)
+
+    fr, wr = copy_read(fetch), copy_read(write)
+    fs, ws = copy_kib / fr, copy_kib / wr
+    alg = 8 * 4096 * 4096
+    out = {
+        "_comment": "HBM traffic per launch of the 4096^2, theta=10, K=8, sigma=50 "
+        "filter. FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 "
+        "--pmc runs of `python3 bench.py --profile-run`, each scaled by the factor "
+        "that makes the same counter read 256 MiB for the 256 MiB device copy in "
+        "that run; written by `python3 bench.py --write-traffic <out>`. source_hash "
+        "identifies the kernel sources the counters were taken from; bench.py "
+        "reports traffic only while it matches.",
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE -d <out>/FETCH_SIZE -o FETCH_SIZE "
+            "--output-format csv -- python3 bench.py --profile-run",
+            "rocprofv3 --pmc WRITE_SIZE -d <out>/WRITE_SIZE -o WRITE_SIZE "
+            "--output-format csv -- python3 bench.py --profile-run",
+            "python3 bench.py --write-traffic <out>",
+        ],
+        "copy_calibration": {"fetch_kib_read": fr, "write_kib_read": wr,
+                             "fetch_scale": fs, "write_scale": ws},
+    }
+    for key, subs in TRAFFIC_KERNELS.items():
+        f = [(n, v) for (_, n), v in fetch.items() if any(x in n for x in subs)]
+        w = [(n, v) for (_, n), v in write.items() if any(x in n for x in subs)]
+        if not f or not w:
+            continue
+        fk, wk = f[0][1], w[0][1]
+        b = int(round((fk * fs + wk * ws) * 1024))
+        out[key] = {"kernel": f[0][0], "source_hash": kernel_source_hash(),
+                    "fetch_kib": fk, "write_kib": wk, "bytes_per_launch": b,
+                    "algorithmic_bytes": alg, "ratio_to_algorithmic": round(b / alg, 4)}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps({k: v.get("ratio_to_algorithmic") for k, v in out.items()
+                      if isinstance(v, dict) and "ratio_to_algorithmic" in v}))
+
+
 def traffic_record(kernel_key, launches_bytes_alg):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when that summary is missing or was taken from other kernel code."""
@@ -98,6 +224,12 @@ def traffic_record(kernel_key, launches_bytes_alg):
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(args.write_traffic)
+        return
+    if args.write_trace_summary:
+        write_trace_summary(*args.write_trace_summary)
+        return
     if args.profile_run:
         profile_run([m for m in args.modes.split(",") if m])
         return

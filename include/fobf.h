@@ -92,6 +92,47 @@ fobf_status fobf_fit(int R, double sigma, int K, double eps, int Tmax,
                      fobf_coef* out);
 
 /*
+ * fobf_fit_period -- the least-squares coefficients of eq. (5) at one given
+ * period T (no scan over T).  T = R is the fixed period [-R, R] of the
+ * earlier Fourier bilateral filter the paper compares against (Sec. III,
+ * Figs. 3-4); there the columns of A are orthogonal on the integers of
+ * [-R, R] and c is the discrete Fourier projection of the samples.  Requires
+ * R >= 1, sigma > 0, 1 <= K <= min(FOBF_KMAX, R+1), T >= max(1, K-1);
+ * FOBF_EINVAL otherwise or when the columns are numerically dependent.
+ * out->Tmax is set to T.  Not cached.
+ */
+fobf_status fobf_fit_period(int R, double sigma, int K, int T, fobf_coef* out);
+
+/*
+ * fobf_lut -- the offline table of optimal parameters (Sec. II, after
+ * Algorithm 1; Fig. 2): K* and T* from Algorithm 1 at every point of a
+ * (sigma, eps) grid.  At run time, (K, T) for an off-grid (sigma, eps) is
+ * read by bilinear interpolation in (sigma, log(1/eps)) -- K rounded up, T
+ * to the nearest integer and at least K - 1 -- and the coefficients come
+ * from one least-squares solve at that (K, T).  The paper reports a loss of
+ * at most 1-2 dB against the exact optimum.
+ *
+ * fobf_lut_create: sigmas[n_sigma] > 0 strictly increasing, eps[n_eps] > 0
+ *   strictly decreasing, Tmax <= 0 = 4R.  Runs Algorithm 1 (fobf_fit with
+ *   K = 0) at every grid point; FOBF_EINVAL if a point has no order up to
+ *   FOBF_KMAX.  The table is owned by the caller (fobf_lut_destroy).
+ * fobf_lut_get: (K*, T*) stored at grid point (i_sigma, i_eps).
+ * fobf_lut_fit: coefficients for (sigma, eps) inside the grid (FOBF_EINVAL
+ *   outside); FOBF_WARN_TOL when the interpolated (K, T) misses E <= eps
+ *   (out is valid; fobf_fit with K = 0 gives the exact optimum).
+ * fobf_lut_save / fobf_lut_load: text file round trip (load allocates).
+ * A table is read-only after creation: concurrent lut_fit calls are safe.
+ */
+typedef struct fobf_lut fobf_lut;
+fobf_status fobf_lut_create(int R, const double* sigmas, int n_sigma, const double* eps,
+                            int n_eps, int Tmax, fobf_lut** out);
+fobf_status fobf_lut_get(const fobf_lut* lut, int i_sigma, int i_eps, int* K, int* T);
+fobf_status fobf_lut_fit(const fobf_lut* lut, double sigma, double eps, fobf_coef* out);
+fobf_status fobf_lut_save(const fobf_lut* lut, const char* path);
+fobf_status fobf_lut_load(const char* path, fobf_lut** out);
+void fobf_lut_destroy(fobf_lut* lut);
+
+/*
  * fobf_fit_cache_clear -- drops every cached fobf_fit result and returns how
  * many there were.  Later fobf_fit calls solve eq. (5) again.  Servers keep
  * their own device copies of coefficients they already use; those are not

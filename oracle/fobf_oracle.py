@@ -17,6 +17,9 @@ eye, in float64:
                           the range kernel, and the scan over the period T
                           of eq. (6) for fixed K.
 * ``algorithm1``          Algorithm 1: smallest K with e(K) <= eps.
+* ``lut_build`` /
+  ``lut_fit``             the offline (sigma, eps) -> (K*, T*) table and its
+                          bilinear read-out (Sec. II, after Algorithm 1).
 * ``fourier_direct``      the K-term shiftable filter (eq. (1) with the
                           cosine series of eq. (3) as range kernel, written
                           as spatial convolutions, Sec. II first paragraph),
@@ -36,6 +39,8 @@ Readings of points the paper leaves open (each one is listed in the design doc):
 4. Ties in the T scan: the smallest T among exactly equal errors.
 5. The filter output is N/D literally (no clamp); D can be <= 0 where the
    cosine series goes negative.
+6. Table read-out: bilinear in (sigma, log(1/eps)); the interpolated order
+   is rounded up and the period to the nearest integer (at least K - 1).
 """
 from __future__ import annotations
 
@@ -241,6 +246,62 @@ def algorithm1(R: int, sigma_or_samples, eps: float, Tmax: int | None = None,
                 best = {"K": K, "T": T, "c": c, "E": e0}
                 e = e0
     return best
+
+
+def lut_build(R: int, sigmas, eps_list, Tmax: int | None = None):
+    """The offline table of Sec. II (paragraph after Algorithm 1, Fig. 2):
+    (K*, T*) of Algorithm 1 at every (sigma, eps) grid point.  Returns
+    dict(sigmas, eps, K[i][j], T[i][j])."""
+    K = [[0] * len(eps_list) for _ in sigmas]
+    T = [[0] * len(eps_list) for _ in sigmas]
+    for i, s in enumerate(sigmas):
+        for j, e in enumerate(eps_list):
+            r = algorithm1(R, float(s), float(e), Tmax)
+            K[i][j], T[i][j] = r["K"], r["T"]
+    return {"R": R, "sigmas": [float(x) for x in sigmas],
+            "eps": [float(x) for x in eps_list], "K": K, "T": T}
+
+
+def lut_interp(table, sigma: float, eps: float):
+    """Bilinear read-out of the table at an off-grid (sigma, eps), in the
+    coordinates (sigma, log(1/eps)) in which the paper reports K* and T*
+    varying smoothly and almost linearly.  The order is rounded up, the
+    period to the nearest integer (and kept >= K - 1).  Returns (K, T)."""
+    sg = table["sigmas"]
+    L = [-math.log(e) for e in table["eps"]]
+    x, y = float(sigma), -math.log(eps)
+
+    def cell(g, v):
+        if len(g) == 1:
+            if v != g[0]:
+                raise ValueError("outside the table")
+            return 0, 0, 0.0
+        if not (g[0] <= v <= g[-1]):
+            raise ValueError("outside the table")
+        i = 0
+        while i < len(g) - 2 and v >= g[i + 1]:
+            i += 1
+        return i, i + 1, (v - g[i]) / (g[i + 1] - g[i])
+
+    i0, i1, a = cell(sg, x)
+    j0, j1, b = cell(L, y)
+
+    def bil(M):
+        return ((1 - a) * ((1 - b) * M[i0][j0] + b * M[i0][j1])
+                + a * ((1 - b) * M[i1][j0] + b * M[i1][j1]))
+
+    K = int(math.ceil(bil(table["K"]) - 1e-9))
+    T = max(max(1, K - 1), int(math.floor(bil(table["T"]) + 0.5)))
+    return K, T
+
+
+def lut_fit(table, sigma: float, eps: float):
+    """Run-time step of the table: (K, T) by :func:`lut_interp`, then the
+    least-squares coefficients at that (K, T), eq. (5).  Returns dict(K, T,
+    c, E)."""
+    K, T = lut_interp(table, sigma, eps)
+    c, E = fit_E(table["R"], float(sigma), K, T)
+    return {"K": K, "T": T, "c": c, "E": E}
 
 
 # --------------------------------------------------------------------------

@@ -20,6 +20,7 @@ LIB = os.path.join(HERE, "libfobf.so")
 SOURCES = [
     "fobf_api.cpp",
     "fobf_fit.cpp",
+    "fobf_lut.cpp",
     "fobf_valu.hip",
     "fobf_mfma.hip",
     "fobf_batch.hip",

@@ -230,9 +230,35 @@ fobf_status fit_samples_impl(int R, const double* b, int K, double eps,
 }
 
 }  // namespace
+
+// Least-squares fit at one given period (eq. (5) without the scan over T).
+fobf_status fit_at_period(int R, double sigma, int K, int T, double eps, fobf_coef* out) {
+  std::vector<double> b = gaussian_samples(R, sigma);
+  FitWork w;
+  FitOne f = fit_one(R, b.data(), K, T, &w);
+  if (!f.ok) return fail(FOBF_EINVAL, "fobf_fit_period: columns are dependent at this period");
+  fill(out, R, K, T, T, sigma, f);
+  if (!(f.E <= eps)) {
+    set_error("fobf_fit_period: E(K,T) exceeds eps");
+    return FOBF_WARN_TOL;
+  }
+  return FOBF_OK;
+}
+
 }  // namespace fobf
 
 using namespace fobf;
+
+extern "C" fobf_status fobf_fit_period(int R, double sigma, int K, int T, fobf_coef* out) {
+  if (!out) return fail(FOBF_EINVAL, "fobf_fit_period: out is NULL");
+  if (R < 1) return fail(FOBF_EINVAL, "fobf_fit_period: R must be >= 1");
+  if (!(sigma > 0.0) || !std::isfinite(sigma))
+    return fail(FOBF_EINVAL, "fobf_fit_period: sigma must be positive and finite");
+  if (K < 1 || K > FOBF_KMAX || K > R + 1)
+    return fail(FOBF_EINVAL, "fobf_fit_period: K out of range");
+  if (T < std::max(1, K - 1)) return fail(FOBF_EINVAL, "fobf_fit_period: T below max(1, K-1)");
+  return fit_at_period(R, sigma, K, T, INFINITY, out);
+}
 
 extern "C" fobf_status fobf_fit(int R, double sigma, int K, double eps,
                                 int Tmax, fobf_coef* out) {

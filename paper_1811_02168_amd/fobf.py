@@ -35,7 +35,8 @@ EXPORTS = [
     "fobf_tune_reset", "fobf_tune_get", "fobf_serve_create",
     "fobf_serve_submit", "fobf_serve_poll", "fobf_serve_destroy",
     "fobf_serve_get_stats", "fobf_serve_inject_fault", "fobf_last_error",
-    "fobf_version", "fobf_peak",
+    "fobf_version", "fobf_peak", "fobf_fit_period", "fobf_lut_create", "fobf_lut_get",
+    "fobf_lut_fit", "fobf_lut_save", "fobf_lut_load", "fobf_lut_destroy",
 ]
 
 
@@ -123,6 +124,15 @@ def _load():
     bind("fobf_version", [])
     bind("fobf_fit_cache_clear", [])
     bind("fobf_peak", [C.c_int, C.c_void_p, C.POINTER(C.c_double)])
+    bind("fobf_fit_period", [C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(_Coef)])
+    bind("fobf_lut_create", [C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double),
+                             C.c_int, C.c_int, C.POINTER(C.c_void_p)])
+    bind("fobf_lut_get", [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int),
+                          C.POINTER(C.c_int)])
+    bind("fobf_lut_fit", [C.c_void_p, C.c_double, C.c_double, C.POINTER(_Coef)])
+    bind("fobf_lut_save", [C.c_void_p, C.c_char_p])
+    bind("fobf_lut_load", [C.c_char_p, C.POINTER(C.c_void_p)])
+    bind("fobf_lut_destroy", [C.c_void_p], None)
     lib.fobf_last_error.restype = C.c_char_p
     lib.fobf_fit.restype = C.c_int
     lib.fobf_fit_samples.restype = C.c_int
@@ -193,6 +203,62 @@ def fit(R: int, sigma: float, K: int, eps: float = 0.1, Tmax: int = 0) -> Coef:
 def fit_cache_clear() -> int:
     """fobf_fit_cache_clear: drop the host fit cache; returns entries dropped."""
     return int(lib.fobf_fit_cache_clear())
+
+
+def fit_period(R: int, sigma: float, K: int, T: int) -> Coef:
+    """fobf_fit_period: least squares at one period (T = R: the fixed-period
+    filter the paper compares with)."""
+    out = _Coef()
+    _check(lib.fobf_fit_period(int(R), float(sigma), int(K), int(T), C.byref(out)))
+    return Coef._from(out, OK)
+
+
+class Lut:
+    """fobf_lut: (sigma, eps) -> (K*, T*) table with bilinear read-out."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+
+    @classmethod
+    def create(cls, R, sigmas, eps, Tmax=0):
+        s = np.ascontiguousarray(sigmas, dtype=np.float64)
+        e = np.ascontiguousarray(eps, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib.fobf_lut_create(int(R), s.ctypes.data_as(C.POINTER(C.c_double)), len(s),
+                                   e.ctypes.data_as(C.POINTER(C.c_double)), len(e),
+                                   int(Tmax), C.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def load(cls, path):
+        h = C.c_void_p()
+        _check(lib.fobf_lut_load(str(path).encode(), C.byref(h)))
+        return cls(h.value)
+
+    def get(self, i_sigma, i_eps):
+        K, T = C.c_int(), C.c_int()
+        _check(lib.fobf_lut_get(self._h, int(i_sigma), int(i_eps), C.byref(K), C.byref(T)))
+        return K.value, T.value
+
+    def fit(self, sigma, eps) -> Coef:
+        out = _Coef()
+        st = lib.fobf_lut_fit(self._h, float(sigma), float(eps), C.byref(out))
+        _check(st, (OK, WARN_TOL))
+        return Coef._from(out, st)
+
+    def save(self, path):
+        _check(lib.fobf_lut_save(self._h, str(path).encode()))
+
+    def close(self):
+        if self._h:
+            lib.fobf_lut_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 PEAK_KINDS = {"valu_fma_f32": 0, "valu_sin_f32": 1, "mfma_f32": 2,

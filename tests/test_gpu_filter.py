@@ -199,3 +199,23 @@ def test_c3_full_size_sampled(algo, prec):
         print("C3 full", algo, prec, sigma, T, float(err.max()))
         assert float(err.max()) <= tol(prec)
         assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
+def test_c2_full_size_sampled(algo, prec):
+    """1024^2, theta=5, K=6, sigma in {10, 30, 80}: sampled outputs against
+    eq. (1) with the fitted cosine series, masked where the oracle's D/W is
+    below 0.01 (sigma=10 has pixels with D <= 0)."""
+    cfg = workloads.C2
+    f = cfg.image()
+    Wi = O.blur_weight(*f.shape, cfg.theta)
+    for sigma in cfg.sigmas:
+        T, c = fitted(sigma, cfg.K)
+        got = gpu_filter(f, cfg.theta, cfg.K, T, c, prec=prec, algo=algo)
+        ys, xs = sample_points(*f.shape, 500, 7 + int(sigma))
+        ref, num, den = O.brute_bf_points(f, cfg.theta, O.cosine_series(c, T), ys, xs)
+        mask = den / Wi[ys, xs] >= DMASK
+        err = np.abs(got[ys, xs] - ref)
+        print("C2 full", algo, prec, sigma, T, float(err[mask].max()), int((~mask).sum()))
+        assert float(err[mask].max()) <= tol(prec)
+        assert np.all(np.isfinite(got))
