@@ -94,8 +94,8 @@ def write_trace_summary(stats_csv, bench_json):
                            f"{avg:,.0f} | {int(float(r['MinNs'])):,} | "
                            f"{int(float(r['MaxNs'])):,} | {tf:.1f} | "
                            f"{tf / PEAK_FP32_TFLOPS:.3f} |")
-    out += ["", "The same run's own HIP-event timing (`roofline.kernel_ms`, "
-            f"uninstrumented): fp32 {line['roofline']['kernel_ms']} ms per launch; "
+    out += ["", "HIP-event timing inside the same traced run (`roofline.kernel_ms` "
+            f"of its JSON line): fp32 {line['roofline']['kernel_ms']} ms per launch; "
             + ", ".join(f"{k} {v['kernel_ms']} ms" for k, v in line.get("mixed", {}).items())
             + ".", ""]
     with open(os.path.join(ROOT, "profiles", "fobf_c3_kernel_trace.md"), "w") as fh:

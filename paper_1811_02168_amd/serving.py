@@ -98,12 +98,23 @@ def bench_serving(pool_img: np.ndarray, n: int = 600, warmup: int = 60,
     t_last = max(results[i][4] for i in timed)
     mpix = sum(sizes[i] for i in timed) / 1e6
     queue = [(results[i][2] - results[i][1]) * 1e3 for i in timed]
+    # where the time goes: submit -> admit (queue, waiting for a fit or for
+    # HBM / in-flight room), admit -> start (batch assembly and issue),
+    # start -> done (copies in, kernel, copies out, completion callback)
+    phases = {
+        "queue": queue,
+        "issue": [(results[i][3] - results[i][2]) * 1e3 for i in timed],
+        "device": [(results[i][4] - results[i][3]) * 1e3 for i in timed],
+    }
     return {
         "requests": len(lat), "warmup": warmup, "offered_rate_rps": rate,
         "p50_ms": round(_percentile(lat, 0.50), 3),
         "p99_ms": round(_percentile(lat, 0.99), 3),
         "mean_ms": round(sum(lat) / len(lat), 3),
         "admit_wait_p99_ms": round(_percentile(queue, 0.99), 3),
+        "breakdown_ms": {k: {"p50": round(_percentile(v, 0.5), 3),
+                             "p99": round(_percentile(v, 0.99), 3)}
+                         for k, v in phases.items()},
         "mpix_s": round(mpix / (t_last - t_first), 1),
         "achieved_rps": round(len(lat) / (t_last - t_first), 1),
         "failed": len(bad), "coef_cache": "warm" if warm_cache else "cold",
