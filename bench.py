@@ -126,10 +126,16 @@ def profile_run(modes):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank space removed, so
+    that only code changes invalidate recorded counters."""
+    import re
     h = hashlib.sha256()
     for name in ("fobf_tiles.h", "fobf_mfma.hip", "fobf_api.cpp"):
-        with open(os.path.join(ROOT, "paper_1811_02168_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1811_02168_amd", "csrc", name)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -32,16 +32,18 @@ __global__ __launch_bounds__(MTHREADS, (SH <= 20 ? 2 : 1)) void mfma_f32_kernel(
   f32_tile<SH>(im, tx, ty, nblk, tbl, Bt, At, nd);
 }
 
-// Workgroup width of the staged kernels: eight strips for fp16 (wider
-// tiles share more of the horizontal halo's channel work), four for the
-// two-word bf16 staging whose buffers need the LDS.
-template <typename OT>
-constexpr int staged_waves() { return Stage<OT>::kParts == 1 ? 8 : 4; }
+// Workgroup width of the staged kernels: eight strips (wider tiles share
+// more of the horizontal halo's channel work), except for the two-word
+// bf16 staging at the largest radii (DV = 7), whose registers spill at
+// eight waves: there four are faster (4096^2, theta = 15: 2.23 vs 3.07 ms;
+// at theta = 10 and 13 eight win, 1.28 vs 1.70 and 1.81 vs 1.92 ms).
+template <typename OT, int DV>
+constexpr int staged_waves() { return (Stage<OT>::kParts == 2 && DV >= 7) ? 4 : 8; }
 
 template <typename OT, int DV>
-__global__ __launch_bounds__(64 * staged_waves<OT>()) void mfma_staged_kernel(ImageParams p,
+__global__ __launch_bounds__((64 * staged_waves<OT, DV>())) void mfma_staged_kernel(ImageParams p,
                                                                             int nblk) {
-  constexpr int NW = staged_waves<OT>();
+  constexpr int NW = staged_waves<OT, DV>();
   extern __shared__ float lds[];
   const int ntx = (p.W + NW * MSTRIP - 1) / (NW * MSTRIP);
   const int nty = (p.H + 16 * nblk - 1) / (16 * nblk);
@@ -103,7 +105,7 @@ template <typename OT, int DV>
 fobf_status launch_staged_dv(const ImageParams& p, int nblk, void* stream) {
   static const bool once = (allow_big_lds(mfma_staged_kernel<OT, DV>), true);
   (void)once;
-  constexpr int NW = staged_waves<OT>();
+  constexpr int NW = staged_waves<OT, DV>();
   // the tallest tile whose per-wave N and D still fit next to the staging
   constexpr size_t fixed = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV, NW>();
   constexpr int cap = static_cast<int>((160 * 1024 - fixed) / (sizeof(float) * NW * 2 * 256));

@@ -33,10 +33,10 @@ struct Slot {
 std::mutex g_tune_mu;
 Slot g_table[kPrecs][kDvMax + 1];
 
-// Defaults measured on MI355X at 4096^2, r = 30: fp32 8 blocks (2.04 ms vs
-// 2.65 at 4, 2.16 at 16), fp16 8 blocks (0.98 ms vs 1.13 at 4), bf16 8
-// blocks (1.84 ms vs 2.34 at 4).  Staged launches cap the height at what
-// fits in LDS.
+// Defaults measured on MI355X at 4096^2, r = 30: fp32 8 blocks (1.83 ms vs
+// 1.95 at 6, 2.15 at 4; taller tiles drop to one workgroup per CU), fp16
+// and bf16 8 blocks (fp16 0.78 ms, bf16 1.62 ms vs 1.78 at 6).  Staged
+// launches cap the height at what fits in LDS.
 TuneChoice builtin(int prec, int dv) {
   (void)prec;
   (void)dv;
