@@ -313,3 +313,16 @@ def test_serve_many_cold_keys():
         assert r.T == c.T
         ref = single(F, img, 3.0, K, c.T, c.c, "fp32")
         assert float(np.max(np.abs(o - ref))) <= 1e-3
+
+
+def test_instruction_rate_probes_are_plausible():
+    """fobf_peak: every measured rate is positive and within 10% above the
+    published MI355X figure for its class (the matrix peaks are dense)."""
+    import paper_1811_02168_amd as F
+    published = {"valu_fma_f32": 157.3, "valu_sin_f32": 157.3 / 2, "mfma_f32": 157.3,
+                 "mfma_f16": 2500.0, "mfma_bf16": 2500.0}
+    for kind, peak in published.items():
+        rate = F.peak(kind)
+        print("peak", kind, rate)
+        assert 0.0 < rate <= 1.1 * peak, (kind, rate)
+    assert F.peak("mfma_f32") > 0.5 * 157.3

@@ -210,3 +210,21 @@ def test_serve_without_device_fails_cleanly():
     assert e.value.status in (F.fobf.EHIP, F.fobf.EINVAL)
     with pytest.raises(F.FobfError):
         F.Server(hbm_budget_bytes=0)
+
+
+def test_package_fails_loudly_without_the_library(tmp_path):
+    """A copy of the package without libfobf.so cannot be imported: there is
+    no CPU fallback for any entry point."""
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(ROOT, "paper_1811_02168_amd")
+    dst = tmp_path / "paper_1811_02168_amd"
+    dst.mkdir()
+    for name in os.listdir(src):
+        if name.endswith(".py"):
+            shutil.copy(os.path.join(src, name), dst / name)
+    r = subprocess.run([sys.executable, "-c", "import paper_1811_02168_amd"],
+                       cwd=tmp_path, capture_output=True, text=True)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "no CPU fallback" in r.stderr
