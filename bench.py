@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--write-traffic", metavar="DIR",
                     help="turn the FETCH_SIZE / WRITE_SIZE counter passes of "
                     "--profile-run under DIR (DIR/FETCH_SIZE/*.csv, "
-                    "DIR/WRITE_SIZE/*.csv) into profiles/traffic.json, then exit")
+                    "DIR/WRITE_SIZE/*.csv) into profiles/fobf_c3_hbm_traffic.json, then exit")
     ap.add_argument("--write-trace-summary", nargs=2, metavar=("STATS_CSV", "BENCH_JSON"),
                     help="turn a rocprofv3 --kernel-trace --stats summary of a "
                     "bench run (and that run's JSON line) into "
@@ -147,7 +147,7 @@ TRAFFIC_KERNELS = {            # key -> substrings naming the kernel
 
 
 def write_traffic(d):
-    """profiles/traffic.json from two rocprofv3 --pmc passes of
+    """profiles/fobf_c3_hbm_traffic.json from two rocprofv3 --pmc passes of
     `bench.py --profile-run`: per kernel, FETCH_SIZE and WRITE_SIZE (KiB per
     dispatch) scaled by the factor that makes each counter read 256 MiB for
     the 256 MiB device-to-device copy of the same run."""
@@ -206,7 +206,7 @@ def write_traffic(d):
         out[key] = {"kernel": f[0][0], "source_hash": kernel_source_hash(),
                     "fetch_kib": fk, "write_kib": wk, "bytes_per_launch": b,
                     "algorithmic_bytes": alg, "ratio_to_algorithmic": round(b / alg, 4)}
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    with open(os.path.join(ROOT, "profiles", "fobf_c3_hbm_traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     print(json.dumps({k: v.get("ratio_to_algorithmic") for k, v in out.items()
@@ -216,7 +216,7 @@ def write_traffic(d):
 def traffic_record(kernel_key, launches_bytes_alg):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when that summary is missing or was taken from other kernel code."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", "fobf_c3_hbm_traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
