@@ -384,6 +384,12 @@ struct Stage<_Float16> {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
   __device__ static __forceinline__ _Float16 cvt(float x) { return static_cast<_Float16>(x); }
+  // two staged values as one 32-bit word (round to nearest)
+  __device__ static __forceinline__ void pack2(float x0, float x1, uint32_t (&w)[1]) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 v = {static_cast<_Float16>(x0), static_cast<_Float16>(x1)};
+    w[0] = __builtin_bit_cast(uint32_t, v);
+  }
 };
 
 template <>
@@ -400,6 +406,21 @@ struct Stage<__bf16> {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
   __device__ static __forceinline__ __bf16 cvt(float x) { return static_cast<__bf16>(x); }
+  // two staged values as hi and lo words.  For the staged channels hi is
+  // the truncation of x (its upper 16 bits, one byte permute for the pair)
+  // and lo the remainder x - hi (exact in float32) rounded to bf16: the
+  // pair still carries x to ~2^-17 relative, with fewer conversions than
+  // rounding hi first.
+  __device__ static __forceinline__ void pack2(float x0, float x1, uint32_t (&w)[2]) {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    const uint32_t u0 = __builtin_bit_cast(uint32_t, x0);
+    const uint32_t u1 = __builtin_bit_cast(uint32_t, x1);
+    w[0] = __builtin_amdgcn_perm(u1, u0, 0x07060302u);   // upper halves of u0, u1
+    const float r0 = x0 - __builtin_bit_cast(float, u0 & 0xffff0000u);
+    const float r1 = x1 - __builtin_bit_cast(float, u1 & 0xffff0000u);
+    const b2 v = {static_cast<__bf16>(r0), static_cast<__bf16>(r1)};
+    w[1] = __builtin_bit_cast(uint32_t, v);
+  }
 };
 
 // LDS pitch (elements) of a staged channel row: >= cw, = 24 (mod 64) so
@@ -472,12 +493,11 @@ __device__ __forceinline__ void stage_fetch(const Img& im, int x0, int row0, int
 // channel g, word part h sits at buf[((h * STAGE_CH + g) * 16 + row) * PC +
 // col], col 0 = column x0 - r.  `interior`: the block's items lie inside
 // the image (no masks).
-template <typename OT, int G, int IW>
+template <typename OT, int G, int IW, bool INTERIOR>
 __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shift, int x0,
-                                           int row0, int CWn, int PC, OT* buf, bool interior,
+                                           int row0, int CWn, int PC, OT* buf,
                                            const float (&fvs)[IW]) {
   using S = Stage<OT>;
-  typedef OT o2 __attribute__((ext_vector_type(2)));
   constexpr int NP = S::kParts;
   const int per_row = (CWn + IW - 1) / IW;
   const int it = threadIdx.x;
@@ -487,38 +507,34 @@ __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shi
   const int row = row0 + rr;
   const int col0 = x0 - im.r + c0;
   const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
-  OT ch[NP][G][IW];
+  float x[G][IW];
 #pragma unroll
   for (int j = 0; j < IW; ++j) {
     const bool in =
-        interior || (rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W));
+        INTERIOR || (rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W));
     const float f = in ? fvs[j] : 0.f;
     const float fs = in ? fvs[j] - shift : 0.f;     // f - m, zero outside
-    float x[G];
     if (G == 1) {
-      x[0] = fs;
+      x[0][j] = fs;
     } else {
       float sn, cs;
       sincos_rev(kinv * f, &sn, &cs);
-      x[0] = cs * fs;
-      x[1] = sn * fs;
-      x[2] = in ? cs : 0.f;
-      x[3] = in ? sn : 0.f;
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      ch[0][g][j] = S::cvt(x[g]);
-      if (NP == 2) ch[NP - 1][g][j] = S::cvt(x[g] - static_cast<float>(ch[0][g][j]));
+      x[0][j] = cs * fs;
+      x[1][j] = sn * fs;
+      x[2][j] = in ? cs : 0.f;
+      x[3][j] = in ? sn : 0.f;
     }
   }
   // IW is even and c0 a multiple of IW: pairs of words are 4-byte aligned
 #pragma unroll
-  for (int h = 0; h < NP; ++h)
+  for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      o2* dst = reinterpret_cast<o2*>(buf + ((h * STAGE_CH + g) * 16 + rr) * PC + c0);
+    for (int j = 0; j < IW / 2; ++j) {
+      uint32_t w[NP];
+      S::pack2(x[g][2 * j], x[g][2 * j + 1], w);
 #pragma unroll
-      for (int j = 0; j < IW / 2; ++j) dst[j] = o2{ch[h][g][2 * j], ch[h][g][2 * j + 1]};
+      for (int h = 0; h < NP; ++h)
+        reinterpret_cast<uint32_t*>(buf + ((h * STAGE_CH + g) * 16 + rr) * PC + c0)[j] = w[h];
     }
 }
 
@@ -597,8 +613,10 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
             fo[v] = im.in[static_cast<size_t>(gy) * im.ld_in + gx];
           }
         }
-        stage_block<OT, G, IW>(im, kinv, shift, x0, row0, CWn, PC, buf, block_interior(row0),
-                               fvs);
+        if (block_interior(row0))
+          stage_block<OT, G, IW, true>(im, kinv, shift, x0, row0, CWn, PC, buf, fvs);
+        else
+          stage_block<OT, G, IW, false>(im, kinv, shift, x0, row0, CWn, PC, buf, fvs);
         // next block's loads (the last block reloads its own: branch-free)
         const int rown = y0 - r + 16 * ((q + 1 < QB) ? q + 1 : q);
         stage_fetch<IW>(im, x0, rown, CWn, block_interior(rown), fvs);
