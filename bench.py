@@ -41,7 +41,10 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-images", type=int, default=256)
-    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-requests", type=int, default=4000,
+                    help="timed requests of the warm-cache serving leg (after "
+                    "a tenth as many warm-up requests); the cold-cache leg "
+                    "times a quarter as many")
     ap.add_argument("--modes", default="fp32,fp16,bf16")
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3 counter passes: one 256 MiB device "
@@ -360,8 +363,9 @@ def main():
     if not args.no_serve:
         try:
             from paper_1811_02168_amd import serving as S
-            serving = {"warm": S.bench_serving(f, n=args.serve_requests),
-                       "cold": S.bench_serving(f, n=args.serve_requests // 2,
+            serving = {"warm": S.bench_serving(f, n=args.serve_requests,
+                                               warmup=args.serve_requests // 10),
+                       "cold": S.bench_serving(f, n=args.serve_requests // 4,
                                                warmup=0, warm_cache=False,
                                                seed=2005)}
         except Exception as e:  # reported, never hidden
