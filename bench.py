@@ -9,9 +9,10 @@ all three sigmas: host fit lookup (float64, cached), coefficient upload in
 the kernel arguments, and the fused filter kernel.  Inputs are resident in
 HBM before timing starts.
 
-`value` is the float32 ("plain") throughput; the fp16- and bf16-staged
-("mixed") forms are timed the same way and reported under "mixed", each
-with its max-abs and PSNR against the FP64 oracle on sampled pixels.
+`value` is the float32 ("plain") throughput; the staged ("mixed") forms --
+fp16, two-word bf16 and two-word fp16 -- are timed the same way and
+reported under "mixed", each with its max-abs and PSNR against the FP64
+oracle on sampled pixels.
 
 Prints ONE JSON line.
 """
@@ -45,7 +46,7 @@ def parse():
                     help="timed requests of the warm-cache serving leg (after "
                     "a tenth as many warm-up requests); the cold-cache leg "
                     "times a quarter as many")
-    ap.add_argument("--modes", default="fp32,fp16,bf16")
+    ap.add_argument("--modes", default="fp32,fp16,bf16,fp16x2")
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3 counter passes: one 256 MiB device "
                     "copy (calibrates FETCH_SIZE/WRITE_SIZE), then one launch "
@@ -65,6 +66,7 @@ KERNEL_LABELS = {
     "mfma_f32_kernel_c3": "fp32 (16x16x4 f32 matrix instruction, 19 horizontal steps = r 30)",
     "mfma_staged_f16_c3": "fp16-staged (16x16x32 f16, fp32 accumulation)",
     "mfma_staged_bf16_c3": "bf16 hi+lo staged (16x16x32 bf16, fp32 accumulation)",
+    "mfma_staged_f16x2_c3": "fp16 hi+lo staged (16x16x32 f16, fp32 accumulation)",
 }
 
 
@@ -146,6 +148,8 @@ TRAFFIC_KERNELS = {            # key -> substrings naming the kernel
     "mfma_f32_kernel_c3": ("mfma_f32_kernel<19>", "mfma_f32_kernelILi19E"),
     "mfma_staged_f16_c3": ("mfma_staged_kernel<_Float16, 5>", "mfma_staged_kernelIDF16_Li5E"),
     "mfma_staged_bf16_c3": ("mfma_staged_kernel<__bf16, 5>", "mfma_staged_kernelIDF16bLi5E"),
+    "mfma_staged_f16x2_c3": ("mfma_staged_kernel<fobf::(anonymous namespace)::F16Pair, 5>",
+                             "mfma_staged_kernelINS0_7F16PairELi5E"),
 }
 
 

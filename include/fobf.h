@@ -49,7 +49,9 @@ typedef enum {
 typedef enum {
   FOBF_FP32 = 0,        /* channels and intermediates stored in float32     */
   FOBF_FP16_STAGE = 1,  /* channels/intermediates staged in fp16, fp32 acc  */
-  FOBF_BF16_STAGE = 2   /* channels/intermediates staged in bf16, fp32 acc  */
+  FOBF_BF16_STAGE = 2,  /* staged as two bf16 words (hi + lo), fp32 acc      */
+  FOBF_FP16X2_STAGE = 3 /* staged as two fp16 words (hi + lo), fp32 acc:
+                           float32-class accuracy on the fp16 matrix cores  */
 } fobf_prec;
 
 typedef enum {
@@ -168,6 +170,11 @@ fobf_status fobf_fit_samples(int R, const double* b, int K, double eps,
  * K, T   order and period parameter, 1 <= K <= FOBF_KMAX, T >= 1.
  * c      host array of K doubles (copied before return).
  * prec   fobf_prec; algo fobf_algo (FOBF_ALGO_VALU supports FOBF_FP32 only).
+ *        The staged modes subtract the tile-centre value m from f before
+ *        rounding (exact: N - m D is accumulated, out = N'/D + m); fp16
+ *        words hold magnitudes below 65504, so the fp16 modes suit images
+ *        whose local contrast times the tap sum (~2.5 theta) stays below
+ *        that, e.g. 8- to 12-bit intensities.
  * stream hipStream_t as void* (NULL = null stream).
  * H, W >= 1, ld >= W.  H == 0 or W == 0 is a no-op returning FOBF_OK.
  */

@@ -1,13 +1,13 @@
 """MI355X (gfx950) Fourier bilateral filter: HIP kernels behind a C ABI
 (include/fobf.h) with a thin ctypes binding.  Importing the package loads
 libfobf.so and fails loudly if it has not been built."""
-from .fobf import (ALGO_AUTO, ALGO_MFMA, ALGO_VALU, BF16_STAGE, FP16_STAGE,
+from .fobf import (ALGO_AUTO, ALGO_MFMA, ALGO_VALU, BF16_STAGE, FP16_STAGE, FP16X2_STAGE,
                    FP32, KMAX, RMAX, Coef, FobfError, Server, autotune,
                    batch_workspace_size, filter, filter_batch, fit,
                    fit_cache_clear, fit_period, fit_samples, Lut, last_error, lib, make_job, peak, tune_get,
                    tune_load, tune_reset, tune_save)
 
-__all__ = ["ALGO_AUTO", "ALGO_MFMA", "ALGO_VALU", "BF16_STAGE", "FP16_STAGE",
+__all__ = ["ALGO_AUTO", "ALGO_MFMA", "ALGO_VALU", "BF16_STAGE", "FP16_STAGE", "FP16X2_STAGE",
            "FP32", "KMAX", "RMAX", "Coef", "FobfError", "Server", "autotune",
            "batch_workspace_size", "filter", "filter_batch", "fit",
            "fit_cache_clear", "fit_period", "fit_samples", "Lut", "last_error", "lib", "make_job", "peak", "tune_get",

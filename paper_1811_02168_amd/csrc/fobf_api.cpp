@@ -75,7 +75,7 @@ fobf_status validate_filter(const float* in, const float* out, int H, int W,
   if (!c) return fail(FOBF_EINVAL, "fobf_filter: c is NULL");
   for (int k = 0; k < K; ++k)
     if (!std::isfinite(c[k])) return fail(FOBF_EINVAL, "fobf_filter: non-finite coefficient");
-  if (prec < FOBF_FP32 || prec > FOBF_BF16_STAGE)
+  if (prec < FOBF_FP32 || prec > FOBF_FP16X2_STAGE)
     return fail(FOBF_EINVAL, "fobf_filter: unknown precision");
   if (algo < FOBF_ALGO_AUTO || algo > FOBF_ALGO_MFMA)
     return fail(FOBF_EINVAL, "fobf_filter: unknown algorithm");

@@ -41,7 +41,8 @@ namespace {
 
 constexpr int BATCH_NBLK_MAX = 8;
 constexpr size_t COUNTER_BYTES = 256;   // one counter per launch, own line
-constexpr int MAX_LAUNCHES = 6;         // 3 precisions x 2 radius classes
+// one counter per launch class: each precision x two radius classes
+constexpr int MAX_LAUNCHES = 2 * kNumPrecisions;
 
 __global__ void reset_counter(int* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
@@ -101,8 +102,10 @@ __global__ __launch_bounds__(MTHREADS, 1) void batch_kernel(const BatchJob* __re
         default: break;
       }
     } else {
-      typedef typename std::conditional<PREC == FOBF_FP16_STAGE, _Float16, __bf16>::type OT;
-      OT* sbuf = reinterpret_cast<OT*>(lds + LDS_TABLE);
+      typedef typename std::conditional<
+          PREC == FOBF_FP16_STAGE, _Float16,
+          typename std::conditional<PREC == FOBF_BF16_STAGE, __bf16, F16Pair>::type>::type OT;
+      typename Stage<OT>::T* sbuf = reinterpret_cast<typename Stage<OT>::T*>(lds + LDS_TABLE);
       float* nd = lds + LDS_TABLE + staged_buf_bytes<OT, DVHI, MWAVES>() / sizeof(float);
       switch (dv) {
 #define FOBF_ST_CASE(D)                                               \
@@ -128,7 +131,8 @@ template <int PREC, int DVHI>
 constexpr size_t batch_fixed_lds() {
   if (PREC == FOBF_FP32) return sizeof(float) * (LDS_TABLE + 8 * DVHI * 64);
   if (PREC == FOBF_FP16_STAGE) return sizeof(float) * LDS_TABLE + staged_buf_bytes<_Float16, DVHI, MWAVES>();
-  return sizeof(float) * LDS_TABLE + staged_buf_bytes<__bf16, DVHI, MWAVES>();
+  if (PREC == FOBF_BF16_STAGE) return sizeof(float) * LDS_TABLE + staged_buf_bytes<__bf16, DVHI, MWAVES>();
+  return sizeof(float) * LDS_TABLE + staged_buf_bytes<F16Pair, DVHI, MWAVES>();
 }
 
 // tallest tile (16-row blocks) whose N/D still fits the 160 KB of LDS
@@ -178,8 +182,10 @@ int class_nblk_cap(int prec, bool large) {
     case FOBF_FP32: return large ? batch_nblk_cap<FOBF_FP32, 7>() : batch_nblk_cap<FOBF_FP32, 4>();
     case FOBF_FP16_STAGE:
       return large ? batch_nblk_cap<FOBF_FP16_STAGE, 7>() : batch_nblk_cap<FOBF_FP16_STAGE, 4>();
-    default:
+    case FOBF_BF16_STAGE:
       return large ? batch_nblk_cap<FOBF_BF16_STAGE, 7>() : batch_nblk_cap<FOBF_BF16_STAGE, 4>();
+    default:
+      return large ? batch_nblk_cap<FOBF_FP16X2_STAGE, 7>() : batch_nblk_cap<FOBF_FP16X2_STAGE, 4>();
   }
 }
 
@@ -188,8 +194,10 @@ BatchLauncher launcher_for(int prec, bool large) {
     case FOBF_FP32: return large ? launch_batch<FOBF_FP32, 5, 7> : launch_batch<FOBF_FP32, 2, 4>;
     case FOBF_FP16_STAGE:
       return large ? launch_batch<FOBF_FP16_STAGE, 5, 7> : launch_batch<FOBF_FP16_STAGE, 2, 4>;
-    default:
+    case FOBF_BF16_STAGE:
       return large ? launch_batch<FOBF_BF16_STAGE, 5, 7> : launch_batch<FOBF_BF16_STAGE, 2, 4>;
+    default:
+      return large ? launch_batch<FOBF_FP16X2_STAGE, 5, 7> : launch_batch<FOBF_FP16X2_STAGE, 2, 4>;
   }
 }
 
@@ -271,6 +279,8 @@ fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t 
   fobf_status up = upload_async(d_table, table.data(), sizeof(BatchJob) * table.size(), stream);
   if (up != FOBF_OK) return up;
   for (const Launch& L : launches) {
+    if (L.cls < 0 || L.cls >= MAX_LAUNCHES)
+      return fail(FOBF_EINTERNAL, "fobf_filter_batch: launch class without a counter");
     BatchLauncher fn = launcher_for(L.cls / 2, L.cls % 2 == 1);
     int* ctr = reinterpret_cast<int*>(base + COUNTER_BYTES * L.cls);
     fobf_status st = fn(d_table + L.first, L.count, L.total, ctr, stream);

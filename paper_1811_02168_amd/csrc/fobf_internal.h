@@ -9,6 +9,10 @@
 
 namespace fobf {
 
+// Number of fobf_prec values (FOBF_FP32 .. FOBF_FP16X2_STAGE): sizes every
+// per-precision table and the batch launch counters.
+constexpr int kNumPrecisions = FOBF_FP16X2_STAGE + 1;
+
 // Thread-local error message behind fobf_last_error().
 void set_error(const std::string& msg);
 fobf_status fail(fobf_status st, const std::string& msg);

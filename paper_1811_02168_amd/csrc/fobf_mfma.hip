@@ -50,7 +50,7 @@ __global__ __launch_bounds__((64 * staged_waves<OT, DV>())) void mfma_staged_ker
   int tx, ty;
   if (!tile_of_block(blockIdx.x, gridDim.x, ntx, nty, &tx, &ty)) return;
   float* tbl = lds;
-  OT* sbuf = reinterpret_cast<OT*>(lds + LDS_TABLE);
+  typename Stage<OT>::T* sbuf = reinterpret_cast<typename Stage<OT>::T*>(lds + LDS_TABLE);
   float* nd = lds + LDS_TABLE + staged_buf_bytes<OT, DV, NW>() / sizeof(float);
   FOBF_LOAD_TABLES(p, tbl);
   const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
@@ -137,6 +137,7 @@ fobf_status launch_mfma(const ImageParams& p, int prec, int nblk, void* stream) 
   if (nblk < 1 || nblk > 16) return fail(FOBF_EINVAL, "fobf_filter: tile height out of range");
   if (prec == FOBF_FP16_STAGE) return launch_staged<_Float16>(p, DV, nblk, stream);
   if (prec == FOBF_BF16_STAGE) return launch_staged<__bf16>(p, DV, nblk, stream);
+  if (prec == FOBF_FP16X2_STAGE) return launch_staged<F16Pair>(p, DV, nblk, stream);
   static const auto table = f32_table(std::make_integer_sequence<int, kMaxSH - kMinSH + 1>{});
   const int SH = (MSTRIP + 2 * p.r + 3) / 4;
   if (SH < kMinSH || SH > kMaxSH)

@@ -432,7 +432,7 @@ extern "C" fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad sigma");
   if (req->K < 1 || req->K > FOBF_KMAX || req->K > s->cfg.R + 1)
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad K");
-  if (req->prec < FOBF_FP32 || req->prec > FOBF_BF16_STAGE)
+  if (req->prec < FOBF_FP32 || req->prec > FOBF_FP16X2_STAGE)
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad precision");
   const size_t bytes = 2 * sizeof(float) * static_cast<size_t>(req->H) * req->W;
   if (bytes > s->cfg.hbm_budget_bytes)

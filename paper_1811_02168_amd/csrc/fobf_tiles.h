@@ -378,6 +378,7 @@ struct Stage;
 
 template <>
 struct Stage<_Float16> {
+  typedef _Float16 T;                     // staged word
   typedef h8 v8;
   static constexpr int kParts = 1;        // one fp16 word per staged value
   __device__ static __forceinline__ f4 mfma(v8 a, v8 b, f4 c) {
@@ -394,6 +395,7 @@ struct Stage<_Float16> {
 
 template <>
 struct Stage<__bf16> {
+  typedef __bf16 T;
   typedef b8 v8;
   // bf16 keeps 8 mantissa bits (relative rounding 2^-9).  The output
   // divides N by D, and where D/W is small (a pixel unlike most of its
@@ -420,6 +422,32 @@ struct Stage<__bf16> {
     const float r1 = x1 - __builtin_bit_cast(float, u1 & 0xffff0000u);
     const b2 v = {static_cast<__bf16>(r0), static_cast<__bf16>(r1)};
     w[1] = __builtin_bit_cast(uint32_t, v);
+  }
+};
+
+// Two-word fp16 staging: every staged value, tap and horizontal result is
+// held as hi + lo fp16 words (hi rounded to nearest, lo the rounded
+// remainder: v = hi + lo to ~2^-22 relative) and products are hi*hi +
+// hi*lo + lo*hi on the fp16 matrix cores -- float32-class accuracy from
+// the staged kernel.  The tag selects this mode; the words are _Float16.
+struct F16Pair {};
+
+template <>
+struct Stage<F16Pair> {
+  typedef _Float16 T;
+  typedef h8 v8;
+  static constexpr int kParts = 2;
+  __device__ static __forceinline__ f4 mfma(v8 a, v8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ _Float16 cvt(float x) { return static_cast<_Float16>(x); }
+  __device__ static __forceinline__ void pack2(float x0, float x1, uint32_t (&w)[2]) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 hi = {static_cast<_Float16>(x0), static_cast<_Float16>(x1)};
+    const h2 lo = {static_cast<_Float16>(x0 - static_cast<float>(hi[0])),
+                   static_cast<_Float16>(x1 - static_cast<float>(hi[1]))};
+    w[0] = __builtin_bit_cast(uint32_t, hi);
+    w[1] = __builtin_bit_cast(uint32_t, lo);
   }
 };
 
@@ -459,7 +487,7 @@ constexpr int staged_bufs() { return 1; }
 
 template <typename OT, int DV, int NW>
 constexpr size_t staged_buf_bytes() {
-  return sizeof(OT) * staged_bufs<OT, NW>() * Stage<OT>::kParts * STAGE_CH * 16 *
+  return sizeof(typename Stage<OT>::T) * staged_bufs<OT, NW>() * Stage<OT>::kParts * STAGE_CH * 16 *
          stage_pitch(stage_width<DV, NW>());
 }
 
@@ -495,7 +523,7 @@ __device__ __forceinline__ void stage_fetch(const Img& im, int x0, int row0, int
 // the image (no masks).
 template <typename OT, int G, int IW, bool INTERIOR>
 __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shift, int x0,
-                                           int row0, int CWn, int PC, OT* buf,
+                                           int row0, int CWn, int PC, typename Stage<OT>::T* buf,
                                            const float (&fvs)[IW]) {
   using S = Stage<OT>;
   constexpr int NP = S::kParts;
@@ -540,11 +568,12 @@ __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shi
 
 template <typename OT, int DV, int G, int NW>
 __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, int x0, int y0,
-                                             int nblk, const float* tbl, OT* sbuf, float* Ns,
+                                             int nblk, const float* tbl,
+                                             typename Stage<OT>::T* sbuf, float* Ns,
                                              float* Ds) {
   using S = Stage<OT>;
   typedef typename S::v8 v8;
-  typedef OT o4 __attribute__((ext_vector_type(4)));
+  typedef typename S::T o4 __attribute__((ext_vector_type(4)));
   constexpr int SHS = (DV + 1) / 2;          // 32-column horizontal steps
   constexpr int NV = (DV + 1) / 2;           // vertical MFMAs (2 blocks each)
   constexpr int PC = stage_pitch(stage_width<DV, NW>());
@@ -598,7 +627,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
       const int q = qq + u;
       if (q < QB) {
         constexpr int NBUF = staged_bufs<OT, NW>();
-        OT* buf = sbuf + (NBUF == 2 ? (q & 1) : 0) * (NS * STAGE_CH * 16 * PC);
+        typename S::T* buf = sbuf + (NBUF == 2 ? (q & 1) : 0) * (NS * STAGE_CH * 16 * PC);
         const int row0 = y0 - r + 16 * q;
         const int pb = q - (DV - 1);
         // output-pixel values for this block's fold, loaded before the
@@ -708,7 +737,8 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 
 template <typename OT, int DV, int NW>
 __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int nblk,
-                                            const float* tbl, OT* sbuf, float* nd) {
+                                            const float* tbl, typename Stage<OT>::T* sbuf,
+                                            float* nd) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int TYo = 16 * nblk;

@@ -21,7 +21,7 @@
 namespace fobf {
 namespace {
 
-constexpr int kPrecs = 3;
+constexpr int kPrecs = kNumPrecisions;
 constexpr int kDvMax = 7;   // dv for r = FOBF_RMAX = 48
 
 struct Slot {
@@ -116,7 +116,7 @@ fobf_status upload_async(void* dst, const void* src, size_t bytes, void* stream)
 using namespace fobf;
 
 extern "C" fobf_status fobf_autotune(int prec, int H, int W, int K, void* hip_stream) {
-  if (prec < FOBF_FP32 || prec > FOBF_BF16_STAGE)
+  if (prec < FOBF_FP32 || prec > FOBF_FP16X2_STAGE)
     return fail(FOBF_EINVAL, "fobf_autotune: unknown precision");
   if (H < 16 || W < 16 || K < 1 || K > FOBF_KMAX)
     return fail(FOBF_EINVAL, "fobf_autotune: need H, W >= 16 and 1 <= K <= FOBF_KMAX");

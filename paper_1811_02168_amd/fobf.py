@@ -19,14 +19,14 @@ LIB_PATH = os.path.join(HERE, "libfobf.so")
 KMAX = 32
 RMAX = 48
 
-FP32, FP16_STAGE, BF16_STAGE = 0, 1, 2
+FP32, FP16_STAGE, BF16_STAGE, FP16X2_STAGE = 0, 1, 2, 3
 ALGO_AUTO, ALGO_VALU, ALGO_MFMA = 0, 1, 2
 
 OK, WARN_TOL, EBUSY = 0, 1, 2
 EINVAL, ENOMEM, EHIP, EINTERNAL, ECANCELED = -1, -2, -3, -4, -5
 
 _PREC = {"fp32": FP32, "f32": FP32, "fp16": FP16_STAGE, "f16": FP16_STAGE,
-         "bf16": BF16_STAGE}
+         "bf16": BF16_STAGE, "fp16x2": FP16X2_STAGE}
 _ALGO = {"auto": ALGO_AUTO, "valu": ALGO_VALU, "mfma": ALGO_MFMA}
 
 EXPORTS = [

@@ -42,7 +42,7 @@ def small_batch(n=18, seed=5):
     return jobs
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16", "fp16x2"])
 def test_batch_matches_single(prec):
     import torch
     import paper_1811_02168_amd as F
@@ -78,7 +78,7 @@ def test_batch_mixed_precisions_and_edge_jobs():
     jobs = small_batch(n=9, seed=8)
     descs, outs, refs = [], [], []     # each job keeps its tensors alive
     for i, (f, theta, sigma, K) in enumerate(jobs):
-        prec = ["fp32", "fp16", "bf16"][i % 3]
+        prec = ["fp32", "fp16", "bf16", "fp16x2"][i % 4]
         coef = F.fit(255, sigma, K, eps=1e9)
         img = dev_img(f)
         out = torch.zeros_like(img)

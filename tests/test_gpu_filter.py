@@ -60,12 +60,14 @@ def fitted(sigma, K):
 
 ALGOS = ["valu", "mfma"]
 # (algorithm, precision) pairs under test, and their max-abs bounds
-MODES = [("valu", "fp32"), ("mfma", "fp32"), ("mfma", "fp16"), ("mfma", "bf16")]
+MODES = [("valu", "fp32"), ("mfma", "fp32"), ("mfma", "fp16"), ("mfma", "bf16"),
+         ("mfma", "fp16x2")]
 MODE_IDS = [f"{a}-{p}" for a, p in MODES]
 
 
 def tol(prec):
-    return TOL_F32 if prec == "fp32" else TOL
+    # the two-word fp16 staging is held to the float32 bound
+    return TOL_F32 if prec in ("fp32", "fp16x2") else TOL
 
 
 @pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
@@ -157,7 +159,7 @@ def test_constant_image_fixed_point(algo, prec):
     assert np.max(np.abs(got - 143.0)) < (1e-3 if prec == "fp32" else 0.05)
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp16x2"])
 def test_staged_against_fp32_kernel(prec):
     """The mixed-precision forms stay within the contract of the plain
     float32 kernel's output (C3 parameters, 512^2 crop)."""
@@ -232,7 +234,7 @@ def test_filter_in_a_captured_graph():
     f = cfg.image()[:300, :260].astype(np.float32)
     T, c = fitted(30.0, cfg.K)
     img = torch.from_numpy(f).cuda()
-    outs = {p: torch.empty_like(img) for p in ("fp32", "fp16", "bf16")}
+    outs = {p: torch.empty_like(img) for p in ("fp32", "fp16", "bf16", "fp16x2")}
     for p, o in outs.items():                    # warm-up (eager)
         F.filter(img, cfg.theta, cfg.K, T, c, prec=p, out=o)
     torch.cuda.synchronize()
