@@ -30,8 +30,9 @@
 //   in each lane (trig never stored); N, D live in LDS.
 // staged paths (16x16x32 f16 / bf16, f32 accumulation): the workgroup
 //   builds each 16-row block of channels once into LDS in the staging
-//   type (shared by all its strips), horizontal results are rounded to
-//   the staging type for the vertical product; N and D live in LDS.
+//   type (shared by all its strips) -- one fp16 word, or hi + lo words of
+//   bf16 or fp16 -- horizontal results are rounded the same way for the
+//   vertical product; N and D live in LDS.
 // In both, channel f (k = 0) forms a group of its own without trig, and
 // every k >= 1 forms a group of four channels sharing one sin/cos.
 
