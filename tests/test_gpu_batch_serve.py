@@ -168,7 +168,7 @@ def serve_requests(n=40, seed=3):
         theta = float(rng.uniform(1.0, 10.0))
         sigma = float(round(rng.uniform(10, 100)))
         K = int(rng.choice([4, 6, 8]))
-        prec = "fp16" if i % 2 else "fp32"
+        prec = ["fp32", "fp16", "bf16", "fp16x2"][i % 4]
         reqs.append((f.astype(np.float32), theta, sigma, K, prec))
     return reqs
 
