@@ -251,3 +251,25 @@ def test_filter_in_a_captured_graph():
             ref = F.filter(img, cfg.theta, cfg.K, T, c, prec=p)
             torch.cuda.synchronize()
             assert torch.equal(o, ref), (rep, p)
+
+
+def test_random_configurations():
+    """Seeded random sizes, radii, orders and range widths (every radius
+    class, ragged tiles, pitched buffers), each checked in every mode
+    against the oracle's filter with the same (K, T, c)."""
+    rng = np.random.default_rng(20181102)
+    for case in range(24):
+        H = int(rng.integers(1, 230))
+        W = int(rng.integers(1, 230))
+        theta = float(rng.uniform(0.3, 16.0))
+        K = int(rng.integers(1, 13))
+        sigma = float(round(rng.uniform(12, 120)))
+        f = workloads.voronoi_image(H, W, max(2, H * W // 300), bool(case % 2), 5000 + case)
+        T, c = fitted(sigma, K)
+        ref, num, den = O.fourier_direct(f, theta, K, T, c, return_nd=True)
+        mask = den / O.blur_weight(H, W, theta) >= DMASK
+        for algo, prec in MODES:
+            got = gpu_filter(f, theta, K, T, c, prec=prec, algo=algo, pad=case % 3)
+            err = float(np.max(np.abs(got - ref)[mask])) if mask.any() else 0.0
+            print("random", case, H, W, round(theta, 2), K, sigma, algo, prec, err)
+            assert err <= tol(prec), (case, H, W, theta, K, sigma, algo, prec, err)
