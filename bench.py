@@ -464,6 +464,20 @@ def batch_leg(F, torch, n):
                 "speedup": round(res["per_image"]["ms"] / res["persistent"]["ms"], 3),
                 "max_abs_batch_vs_single": diff, "autotune_s": round(tune_s, 2),
                 "dtype": "f32"})
+    # the same batch with two-word fp16 staging (float32-class accuracy)
+    descs2 = [F.make_job(img, out, j.theta, j.K, coef.T, coef.c, prec="fp16x2")
+              for img, out, j, coef in items]
+    F.filter_batch(descs2, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        F.filter_batch(descs2, workspace=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / 5
+    d2 = max(float((o - b).abs().max()) for (_, o, _, _), b in zip(items, outs))
+    res["persistent_fp16x2"] = {"ms": round(ms, 3), "mpix_s": round(mpix / ms * 1e3, 1),
+                                "tflops": round(flop / ms / 1e9, 2),
+                                "max_abs_vs_fp32_per_image": d2}
     F.tune_reset()
     return res
 
