@@ -232,3 +232,16 @@ def test_package_fails_loudly_without_the_library(tmp_path):
                        cwd=tmp_path, capture_output=True, text=True)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "no CPU fallback" in r.stderr
+
+
+def test_serving_stream_is_a_seeded_replay():
+    """The Poisson request stream (arrival times, sizes, parameters) is a
+    pure function of its seed, so a serving run can be replayed."""
+    import workloads
+    a = workloads.serve_stream(n=300, seed=1005)
+    b = workloads.serve_stream(n=300, seed=1005)
+    c = workloads.serve_stream(n=300, seed=1006)
+    assert a == b and a != c
+    gaps = np.diff([j.t_arrival for j in a])
+    assert np.all(gaps > 0)
+    assert 0.5 / 200 < float(np.mean(gaps)) < 2.0 / 200     # ~200 req/s

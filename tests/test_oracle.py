@@ -167,6 +167,31 @@ def test_brute_bf_invariants():
     np.testing.assert_allclose(O.brute_bf(f, theta, delta), f, atol=1e-12)
 
 
+def test_brute_bf_matches_four_nested_loops():
+    """eq. (1) written as the plainest possible loops (pixel, then every
+    in-image neighbour of the square window) on a tiny image, with an
+    asymmetric range kernel so that a swapped difference would show."""
+    f = small_image(H=9, W=11, seed=3, ncells=4)
+    theta = 1.2
+    r = O.spatial_radius(theta)
+    kernel = lambda t: np.exp(-(np.asarray(t) - 3.0) ** 2 / 800.0)  # noqa: E731
+    H, W = f.shape
+    ref = np.zeros((H, W))
+    for y in range(H):
+        for x in range(W):
+            num = den = 0.0
+            for jy in range(-r, r + 1):
+                for jx in range(-r, r + 1):
+                    yy, xx = y - jy, x - jx
+                    if 0 <= yy < H and 0 <= xx < W:
+                        w = math.exp(-(jy * jy + jx * jx) / (2 * theta * theta))
+                        wt = w * float(kernel(f[yy, xx] - f[y, x]))
+                        num += wt * f[yy, xx]
+                        den += wt
+            ref[y, x] = num / den
+    np.testing.assert_allclose(O.brute_bf(f, theta, kernel), ref, rtol=1e-13, atol=1e-12)
+
+
 def test_brute_bf_points_matches_full():
     f = small_image()
     theta = 2.2
