@@ -48,8 +48,15 @@ __global__ void reset_counter(int* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
+// Two workgroups per CU (256 VGPRs per lane) for the small radius class,
+// whose tile bodies fit that budget; one for the large class, whose
+// largest radii need more registers.
+template <int DVHI>
+constexpr int batch_min_blocks() { return DVHI <= 4 ? 2 : 1; }
+
 template <int PREC, int DVLO, int DVHI>
-__global__ __launch_bounds__(MTHREADS, 1) void batch_kernel(const BatchJob* __restrict__ jobs,
+__global__ __launch_bounds__(MTHREADS, batch_min_blocks<DVHI>()) void batch_kernel(
+    const BatchJob* __restrict__ jobs,
                                                             int njobs, int total,
                                                             int* __restrict__ counter) {
   extern __shared__ float lds[];
@@ -135,10 +142,12 @@ constexpr size_t batch_fixed_lds() {
   return sizeof(float) * LDS_TABLE + staged_buf_bytes<F16Pair, DVHI, MWAVES>();
 }
 
-// tallest tile (16-row blocks) whose N/D still fits the 160 KB of LDS
+// tallest tile (16-row blocks) whose N/D still fits the LDS share of one
+// workgroup (160 KB over the workgroups per CU the class is built for)
 template <int PREC, int DVHI>
 constexpr int batch_nblk_cap() {
-  constexpr size_t room = 160 * 1024 - 256 - batch_fixed_lds<PREC, DVHI>();
+  constexpr size_t room =
+      160 * 1024 / batch_min_blocks<DVHI>() - 256 - batch_fixed_lds<PREC, DVHI>();
   constexpr int nb = static_cast<int>(room / (sizeof(float) * MWAVES * 2 * 256));
   return nb < BATCH_NBLK_MAX ? nb : BATCH_NBLK_MAX;
 }
