@@ -199,7 +199,8 @@ typedef struct {
  * parameters with persistent launches: every workgroup pulls output tiles
  * from a shared queue that spans all jobs (work stealing), so small and
  * large images, and different radii and orders, share the machine.  All
- * jobs of one precision and radius class (r <= 24, or 24 < r <= 48) go
+ * jobs of one precision and radius class (r <= 24, 24 < r <= 32, or
+ * 32 < r <= 48) go
  * into ONE launch; a batch of one precision and class is one launch.
  *
  * jobs      host array of n jobs (read before return; the job table is

@@ -12,7 +12,8 @@
 // counter passes the last tile.
 //
 // One launch serves all jobs of one precision whose radius class fits the
-// kernel: DV = ceil((16 + 2r) / 16) <= 4 (r <= 24) or 5 <= DV <= 7 (r <= 48).
+// kernel: DV = ceil((16 + 2r) / 16) <= 4 (r <= 24), DV = 5 (r <= 32) or
+// 6 <= DV <= 7 (r <= 48).
 // The float32 body runs with 4*DV horizontal steps (Toeplitz slices past
 // the band are zero), so one instantiation covers a whole radius class.
 #include <hip/hip_runtime.h>
@@ -41,18 +42,22 @@ namespace {
 
 constexpr int BATCH_NBLK_MAX = 8;
 constexpr size_t COUNTER_BYTES = 256;   // one counter per launch, own line
-// one counter per launch class: each precision x two radius classes
-constexpr int MAX_LAUNCHES = 2 * kNumPrecisions;
+// Radius classes of the batch launches (DV = ceil((16 + 2r)/16)): r <= 24,
+// 24 < r <= 32, 32 < r <= 48.  One counter per launch class: each
+// precision x each radius class.
+constexpr int kRadiusClasses = 3;
+constexpr int radius_class(int dv) { return dv <= 4 ? 0 : (dv == 5 ? 1 : 2); }
+constexpr int MAX_LAUNCHES = kRadiusClasses * kNumPrecisions;
 
 __global__ void reset_counter(int* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
-// Two workgroups per CU (256 VGPRs per lane) for the small radius class,
-// whose tile bodies fit that budget; one for the large class, whose
-// largest radii need more registers.
+// Two workgroups per CU (256 VGPRs per lane, half the LDS each) for the
+// radius classes whose tile bodies fit that budget (DV <= 5); one for the
+// largest radii, which need more registers.
 template <int DVHI>
-constexpr int batch_min_blocks() { return DVHI <= 4 ? 2 : 1; }
+constexpr int batch_min_blocks() { return DVHI <= 5 ? 2 : 1; }
 
 template <int PREC, int DVLO, int DVHI>
 __global__ __launch_bounds__(MTHREADS, batch_min_blocks<DVHI>()) void batch_kernel(
@@ -186,27 +191,40 @@ fobf_status launch_batch(const BatchJob* d_jobs, int njobs, int total, int* d_co
 
 typedef fobf_status (*BatchLauncher)(const BatchJob*, int, int, int*, void*);
 
-int class_nblk_cap(int prec, bool large) {
-  switch (prec) {
-    case FOBF_FP32: return large ? batch_nblk_cap<FOBF_FP32, 7>() : batch_nblk_cap<FOBF_FP32, 4>();
-    case FOBF_FP16_STAGE:
-      return large ? batch_nblk_cap<FOBF_FP16_STAGE, 7>() : batch_nblk_cap<FOBF_FP16_STAGE, 4>();
-    case FOBF_BF16_STAGE:
-      return large ? batch_nblk_cap<FOBF_BF16_STAGE, 7>() : batch_nblk_cap<FOBF_BF16_STAGE, 4>();
-    default:
-      return large ? batch_nblk_cap<FOBF_FP16X2_STAGE, 7>() : batch_nblk_cap<FOBF_FP16X2_STAGE, 4>();
+// per (precision, radius class): tile-height cap and launcher
+template <int PREC>
+int class_nblk_cap_p(int cidx) {
+  switch (cidx) {
+    case 0: return batch_nblk_cap<PREC, 4>();
+    case 1: return batch_nblk_cap<PREC, 5>();
+    default: return batch_nblk_cap<PREC, 7>();
   }
 }
 
-BatchLauncher launcher_for(int prec, bool large) {
+int class_nblk_cap(int prec, int cidx) {
   switch (prec) {
-    case FOBF_FP32: return large ? launch_batch<FOBF_FP32, 5, 7> : launch_batch<FOBF_FP32, 2, 4>;
-    case FOBF_FP16_STAGE:
-      return large ? launch_batch<FOBF_FP16_STAGE, 5, 7> : launch_batch<FOBF_FP16_STAGE, 2, 4>;
-    case FOBF_BF16_STAGE:
-      return large ? launch_batch<FOBF_BF16_STAGE, 5, 7> : launch_batch<FOBF_BF16_STAGE, 2, 4>;
-    default:
-      return large ? launch_batch<FOBF_FP16X2_STAGE, 5, 7> : launch_batch<FOBF_FP16X2_STAGE, 2, 4>;
+    case FOBF_FP32: return class_nblk_cap_p<FOBF_FP32>(cidx);
+    case FOBF_FP16_STAGE: return class_nblk_cap_p<FOBF_FP16_STAGE>(cidx);
+    case FOBF_BF16_STAGE: return class_nblk_cap_p<FOBF_BF16_STAGE>(cidx);
+    default: return class_nblk_cap_p<FOBF_FP16X2_STAGE>(cidx);
+  }
+}
+
+template <int PREC>
+BatchLauncher launcher_for_p(int cidx) {
+  switch (cidx) {
+    case 0: return launch_batch<PREC, 2, 4>;
+    case 1: return launch_batch<PREC, 5, 5>;
+    default: return launch_batch<PREC, 6, 7>;
+  }
+}
+
+BatchLauncher launcher_for(int prec, int cidx) {
+  switch (prec) {
+    case FOBF_FP32: return launcher_for_p<FOBF_FP32>(cidx);
+    case FOBF_FP16_STAGE: return launcher_for_p<FOBF_FP16_STAGE>(cidx);
+    case FOBF_BF16_STAGE: return launcher_for_p<FOBF_BF16_STAGE>(cidx);
+    default: return launcher_for_p<FOBF_FP16X2_STAGE>(cidx);
   }
 }
 
@@ -232,7 +250,7 @@ fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t 
   struct Entry {
     BatchJob b;
     double cost;
-    int cls;      // launch class: prec * 2 + large
+    int cls;      // launch class: prec * kRadiusClasses + radius class
   };
   std::vector<Entry> es;
   es.reserve(n);
@@ -252,12 +270,12 @@ fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t 
     const int r = e.b.p.r;
     e.b.dv = (16 + 2 * r + 15) / 16;
     e.b.nblk = std::min(batch_tile_blocks(j.prec, e.b.dv, j.H),
-                        class_nblk_cap(j.prec, e.b.dv >= 5));
+                        class_nblk_cap(j.prec, radius_class(e.b.dv)));
     e.b.ntx = (j.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP);
     e.b.nty = (j.H + 16 * e.b.nblk - 1) / (16 * e.b.nblk);
     // cost of one tile ~ channels x (halo'd rows) x band
     e.cost = static_cast<double>(4 * j.K - 3) * (e.b.nblk + e.b.dv - 1) * (2 * r + 1);
-    e.cls = j.prec * 2 + (e.b.dv >= 5 ? 1 : 0);
+    e.cls = j.prec * kRadiusClasses + radius_class(e.b.dv);
     es.push_back(e);
   }
   // per class: largest tiles first (their tail is the hardest to hide)
@@ -290,7 +308,7 @@ fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t 
   for (const Launch& L : launches) {
     if (L.cls < 0 || L.cls >= MAX_LAUNCHES)
       return fail(FOBF_EINTERNAL, "fobf_filter_batch: launch class without a counter");
-    BatchLauncher fn = launcher_for(L.cls / 2, L.cls % 2 == 1);
+    BatchLauncher fn = launcher_for(L.cls / kRadiusClasses, L.cls % kRadiusClasses);
     int* ctr = reinterpret_cast<int*>(base + COUNTER_BYTES * L.cls);
     fobf_status st = fn(d_table + L.first, L.count, L.total, ctr, stream);
     if (st != FOBF_OK) return st;

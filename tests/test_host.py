@@ -191,7 +191,7 @@ def test_batch_validation_without_device():
     # the job table (a precision without its own counter would zero the
     # first job's image pointer)
     nprec = len({F.FP32, F.FP16_STAGE, F.BF16_STAGE, F.FP16X2_STAGE})
-    assert F.batch_workspace_size(0) == 256 * 2 * nprec
+    assert F.batch_workspace_size(0) == 256 * 3 * nprec      # three radius classes
     assert F.batch_workspace_size(10) > F.batch_workspace_size(1)
     assert F.lib.fobf_filter_batch(None, 0, None, 0, None) == 0          # no-op
     j = F.fobf._Job()
