@@ -300,8 +300,24 @@ def main():
             "value": nimg * npx / (ms_step * 1e-3) / 1e6,
         }
 
-    for s in cfg.sigmas:                               # fits outside timing
-        F.fit(R, s, K, eps=cfg.eps)
+    # a1, the host fit: cold cost of the period scan per (sigma, K), of
+    # Algorithm 1, and of one read-out of a (sigma, eps) table
+    F.fit_cache_clear()
+    host_fit = {}
+    for s in cfg.sigmas:
+        t0 = time.perf_counter()
+        F.fit(R, s, K, eps=cfg.eps)                    # cached for the steps
+        host_fit[f"scan_K{K}_sigma{s:g}_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    t0 = time.perf_counter()
+    a1 = F.fit(R, 50.0, 0, eps=1e-3)
+    host_fit["algorithm1_sigma50_eps1e-3_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    host_fit["algorithm1_K"] = a1.K
+    lut = F.Lut.create(R, [20.0, 40.0, 80.0], [1e-1, 1e-3])
+    t0 = time.perf_counter()
+    for _ in range(100):
+        lut.fit(33.0, 1e-2)
+    host_fit["table_readout_us"] = round((time.perf_counter() - t0) * 1e4, 1)
+    lut.close()
     modes = [m for m in args.modes.split(",") if m]
     if args.no_mixed:
         modes = ["fp32"]
@@ -397,6 +413,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "accuracy_vs_fp64_oracle": accuracy,
+        "host_fit": host_fit,
         "batch": batch,
         "serving": serving,
     }
