@@ -115,6 +115,7 @@ EDGE = [
     (64, 64, 3.0, 1, 30.0),      # K = 1: plain Gaussian blur
     (70, 90, 1.0, 2, 60.0),      # r = 3
     (40, 200, 5.0, 16, 12.0),    # large K
+    (48, 80, 3.0, 32, 10.0),     # K = FOBF_KMAX
     (150, 120, 16.0, 3, 80.0),   # r = 48, the largest radius
     (33, 65, 0.2, 4, 30.0),      # r = 1
 ]
