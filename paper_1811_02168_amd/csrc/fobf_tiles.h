@@ -486,10 +486,23 @@ constexpr int stage_width() {
 template <typename OT, int NW>
 constexpr int staged_bufs() { return 1; }
 
+// The staging region: the channel buffers, then (two-word modes only) the
+// per-lane vertical Toeplitz slices, which would otherwise hold 24 VGPRs
+// per lane through the whole group at the kernel's register limit.
 template <typename OT, int DV, int NW>
-constexpr size_t staged_buf_bytes() {
+constexpr size_t staged_stage_bytes() {
   return sizeof(typename Stage<OT>::T) * staged_bufs<OT, NW>() * Stage<OT>::kParts * STAGE_CH * 16 *
          stage_pitch(stage_width<DV, NW>());
+}
+
+template <typename OT, int DV>
+constexpr size_t staged_vtap_bytes() {
+  return Stage<OT>::kParts == 2 ? static_cast<size_t>((DV + 1) / 2) * 2 * 64 * 16 : 0;
+}
+
+template <typename OT, int DV, int NW>
+constexpr size_t staged_buf_bytes() {
+  return staged_stage_bytes<OT, DV, NW>() + staged_vtap_bytes<OT, DV>();
 }
 
 // Issues the global loads of this thread's item of one block into
@@ -606,16 +619,28 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
     }
   // vertical weights: MFMA t pairs H blocks 2t (elements 0..3) and 2t+1
   // (elements 4..7); element j <-> H row 16 (2t + j/4) + 4 lk + j%4
+  // (two-word modes: built by wave 0 into the LDS table after the staging
+  // buffers and read back per vertical step)
+  constexpr bool kVtapLds = NS == 2;
   v8 Aw[NV][NS];
+  v8* const vtap = reinterpret_cast<v8*>(reinterpret_cast<char*>(sbuf) +
+                                         staged_stage_bytes<OT, DV, NW>());
+  if (!kVtapLds || wave == 0) {
 #pragma unroll
-  for (int t = 0; t < NV; ++t)
+    for (int t = 0; t < NV; ++t)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int blk = 2 * t + (j >> 2);
-      const float w = blk < DV ? tap(gS, 16 * blk + 4 * lk + (j & 3) - r - li, r) : 0.f;
-      Aw[t][0][j] = S::cvt(w);
-      if (NS == 2) Aw[t][NS - 1][j] = S::cvt(w - static_cast<float>(Aw[t][0][j]));
-    }
+      for (int j = 0; j < 8; ++j) {
+        const int blk = 2 * t + (j >> 2);
+        const float w = blk < DV ? tap(gS, 16 * blk + 4 * lk + (j & 3) - r - li, r) : 0.f;
+        Aw[t][0][j] = S::cvt(w);
+        if (NS == 2) Aw[t][NS - 1][j] = S::cvt(w - static_cast<float>(Aw[t][0][j]));
+      }
+    if (kVtapLds)
+#pragma unroll
+      for (int t = 0; t < NV; ++t)
+#pragma unroll
+        for (int h = 0; h < NS; ++h) vtap[(t * NS + h) * 64 + lane] = Aw[t][h];
+  }
 
   o4 ring[DV][NS][G];
   auto block_interior = [&](int row0) { return cols_in && row0 >= 0 && row0 + 16 <= im.H; };
@@ -690,6 +715,9 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
           for (int t = 0; t < NV; ++t) {
             const int b0 = 2 * t, b1 = (2 * t + 1 < DV) ? 2 * t + 1 : 2 * t;
+            v8 aw[NS];
+#pragma unroll
+            for (int h = 0; h < NS; ++h) aw[h] = kVtapLds ? vtap[(t * NS + h) * 64 + lane] : Aw[t][h];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
               v8 b[NS];
@@ -702,7 +730,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
               for (int ha = 0; ha < NS; ++ha)
 #pragma unroll
-                for (int hb = 0; hb + ha < NS; ++hb) vacc[g] = S::mfma(Aw[t][ha], b[hb], vacc[g]);
+                for (int hb = 0; hb + ha < NS; ++hb) vacc[g] = S::mfma(aw[ha], b[hb], vacc[g]);
             }
           }
           // fold (all reads of N, D before the writes they may alias)
@@ -752,7 +780,7 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
   // by zero taps and are never written, so they must hold finite values
   {
     float4* z = reinterpret_cast<float4*>(sbuf);
-    const int n16 = static_cast<int>(staged_buf_bytes<OT, DV, NW>() / 16);
+    const int n16 = static_cast<int>(staged_stage_bytes<OT, DV, NW>() / 16);
     for (int i = threadIdx.x; i < n16; i += 64 * NW) z[i] = float4{0.f, 0.f, 0.f, 0.f};
   }
   // Staged channels carry (f - m) instead of f, m = f at the tile centre:
