@@ -486,23 +486,28 @@ constexpr int stage_width() {
 template <typename OT, int NW>
 constexpr int staged_bufs() { return 1; }
 
-// The staging region: the channel buffers, then (two-word modes only) the
-// per-lane vertical Toeplitz slices, which would otherwise hold 24 VGPRs
-// per lane through the whole group at the kernel's register limit.
+// The staging region: the channel buffers, then (two-word modes at eight
+// strips only) the per-lane vertical Toeplitz slices, which would otherwise
+// hold 24 VGPRs per lane through the whole group at the kernel's register
+// limit.  Four-strip workgroups (the batch kernel) keep them in registers:
+// there the LDS is worth more as tile height.
 template <typename OT, int DV, int NW>
 constexpr size_t staged_stage_bytes() {
   return sizeof(typename Stage<OT>::T) * staged_bufs<OT, NW>() * Stage<OT>::kParts * STAGE_CH * 16 *
          stage_pitch(stage_width<DV, NW>());
 }
 
-template <typename OT, int DV>
+template <typename OT, int NW>
+constexpr bool staged_vtap_in_lds() { return Stage<OT>::kParts == 2 && NW == 8; }
+
+template <typename OT, int DV, int NW>
 constexpr size_t staged_vtap_bytes() {
-  return Stage<OT>::kParts == 2 ? static_cast<size_t>((DV + 1) / 2) * 2 * 64 * 16 : 0;
+  return staged_vtap_in_lds<OT, NW>() ? static_cast<size_t>((DV + 1) / 2) * 2 * 64 * 16 : 0;
 }
 
 template <typename OT, int DV, int NW>
 constexpr size_t staged_buf_bytes() {
-  return staged_stage_bytes<OT, DV, NW>() + staged_vtap_bytes<OT, DV>();
+  return staged_stage_bytes<OT, DV, NW>() + staged_vtap_bytes<OT, DV, NW>();
 }
 
 // Issues the global loads of this thread's item of one block into
@@ -621,7 +626,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   // (elements 4..7); element j <-> H row 16 (2t + j/4) + 4 lk + j%4
   // (two-word modes: built by wave 0 into the LDS table after the staging
   // buffers and read back per vertical step)
-  constexpr bool kVtapLds = NS == 2;
+  constexpr bool kVtapLds = staged_vtap_in_lds<OT, NW>();
   v8 Aw[NV][NS];
   v8* const vtap = reinterpret_cast<v8*>(reinterpret_cast<char*>(sbuf) +
                                          staged_stage_bytes<OT, DV, NW>());
