@@ -209,7 +209,10 @@ typedef struct {
  *           bytes, 256-byte aligned, caller-owned, not used by another
  *           call until this call's work on the stream has finished.
  * Same rules per job as fobf_filter (algorithm: matrix cores).  Jobs with
- * H == 0 or W == 0 are skipped; n == 0 is a no-op.
+ * H == 0 or W == 0 are skipped; n == 0 is a no-op.  Unlike fobf_filter
+ * (kernels only, capturable in a HIP graph), a batch call copies its job
+ * table from library-owned pinned memory, so it is not meant for graph
+ * capture.
  */
 size_t fobf_batch_workspace_size(int n);
 fobf_status fobf_filter_batch(const fobf_job* jobs, int n, void* d_work,
