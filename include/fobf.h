@@ -177,6 +177,9 @@ fobf_status fobf_fit_samples(int R, const double* b, int K, double eps,
  *        that, e.g. 8- to 12-bit intensities.
  * stream hipStream_t as void* (NULL = null stream).
  * H, W >= 1, ld >= W.  H == 0 or W == 0 is a no-op returning FOBF_OK.
+ * Enqueues kernels only (no allocation, copy or memset), so the call can
+ * be captured in a HIP graph; launch errors are returned, device faults
+ * surface at the caller's next synchronisation.
  */
 fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W,
                         int ld_in, int ld_out, double theta, int K, int T,
