@@ -107,4 +107,4 @@ extern "C" fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W
 
 extern "C" const char* fobf_last_error(void) { return fobf::error_cstr(); }
 
-extern "C" int fobf_version(void) { return 100; }
+extern "C" int fobf_version(void) { return 200; }  // 0.2.0
