@@ -131,11 +131,12 @@ def profile_run(modes):
 
 
 def kernel_source_hash():
-    """Hash of the kernel sources with comments and blank space removed, so
-    that only code changes invalidate recorded counters."""
+    """Hash of the device code and its launch configuration (kernel bodies,
+    launchers, tile-height defaults) with comments and blank space removed,
+    so that only code changes invalidate recorded counters."""
     import re
     h = hashlib.sha256()
-    for name in ("fobf_tiles.h", "fobf_mfma.hip", "fobf_api.cpp"):
+    for name in ("fobf_tiles.h", "fobf_mfma.hip", "fobf_tune.hip"):
         with open(os.path.join(ROOT, "paper_1811_02168_amd", "csrc", name)) as fh:
             src = fh.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
