@@ -264,8 +264,16 @@ void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
       continue;
     }
     const size_t row = sizeof(float) * q->r.W;
-    hipMemcpy2DAsync(q->d_in, row, q->r.h_in, sizeof(float) * q->r.ld_in, row, q->r.H,
-                     hipMemcpyHostToDevice, st);
+    if (hipMemcpy2DAsync(q->d_in, row, q->r.h_in, sizeof(float) * q->r.ld_in, row, q->r.H,
+                         hipMemcpyHostToDevice, st) != hipSuccess) {
+      hipFreeAsync(q->d_in, st);
+      hipFreeAsync(q->d_out, st);
+      q->d_in = q->d_out = nullptr;
+      set_error("fobf_serve: host-to-device copy failed");
+      q->res.status = FOBF_EHIP;
+      bad.push_back(q);
+      continue;
+    }
     fobf_job j{};
     j.d_in = q->d_in;
     j.d_out = q->d_out;
@@ -295,8 +303,11 @@ void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
   for (Req* q : ok) {
     if (st_b == FOBF_OK) {
       const size_t row = sizeof(float) * q->r.W;
-      hipMemcpy2DAsync(q->r.h_out, sizeof(float) * q->r.ld_out, q->d_out, row, row, q->r.H,
-                       hipMemcpyDeviceToHost, st);
+      if (hipMemcpy2DAsync(q->r.h_out, sizeof(float) * q->r.ld_out, q->d_out, row, row,
+                           q->r.H, hipMemcpyDeviceToHost, st) != hipSuccess) {
+        set_error("fobf_serve: device-to-host copy failed");
+        q->res.status = FOBF_EHIP;
+      }
     } else {
       q->res.status = st_b;
     }
