@@ -224,6 +224,39 @@ def test_c2_full_size_sampled(algo, prec):
         assert np.all(np.isfinite(got))
 
 
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
+def test_c3_full_size_symmetries(algo, prec):
+    """4096^2, theta=10, K=8, sigma=50, every output pixel: the filter
+    commutes with row and column flips and with transposition (square,
+    even window; neighbours outside the image excluded), with f -> R - f and
+    with f -> f + a (the series kernel depends on differences of
+    intensities only, and is even).  Each side is within tol(prec) of the
+    exact result (min D/W is 0.12 here, so no pixel is masked), hence the
+    two agree within twice that."""
+    import torch
+    import paper_1811_02168_amd as F
+    cfg = workloads.C3
+    f = torch.from_numpy(cfg.image().astype(np.float32)).cuda()
+    T, c = fitted(50.0, cfg.K)
+
+    def run(x):
+        return F.filter(x.contiguous(), cfg.theta, cfg.K, T, c, prec=prec, algo=algo)
+
+    base = run(f)
+    cases = {
+        "flip rows": (run(torch.flip(f, [0])), torch.flip(base, [0])),
+        "flip cols": (run(torch.flip(f, [1])), torch.flip(base, [1])),
+        "transpose": (run(f.t()), base.t()),
+        "R - f": (run(255.0 - f), 255.0 - base),
+        "f + 37": (run(f + 37.0), base + 37.0),
+    }
+    torch.cuda.synchronize()
+    for name, (a, b) in cases.items():
+        d = float((a - b).abs().max())
+        print("C3 symmetry", algo, prec, name, d)
+        assert math.isfinite(d) and d <= 2 * tol(prec), name
+
+
 def test_filter_in_a_captured_graph():
     """fobf_filter enqueues kernels only (no allocation, no memset), so a
     caller can capture it in a HIP graph: three precisions captured once,
