@@ -265,9 +265,9 @@ def main():
     H, W = cfg.H, cfg.W
     npx = H * W
     f = cfg.image()
-    cpu = None
+    cpu, refs = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_timing_leg(f, cfg)
+        cpu, refs = cpu_baseline_leg(f, cfg)
         print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
     dev = torch.device("cuda")
     img = torch.from_numpy(f.astype(np.float32)).to(dev)
@@ -370,7 +370,7 @@ def main():
 
     accuracy = None
     if not args.no_cpu_baseline:
-        accuracy = accuracy_leg(f, cfg, modes, outs, step, F, torch)
+        accuracy = accuracy_leg(img, cfg, modes, refs, F, torch)
 
     batch = None
     if not args.no_batch:
@@ -527,13 +527,28 @@ def _oracle_parallel(img, theta, K, T, c, nproc):
     return np.concatenate(parts, axis=0), time.perf_counter() - t0
 
 
-def cpu_timing_leg(f, cfg):
-    """Times the FP64 oracle on a bounded sample of the workload, on one core
-    and on every host core.  Runs before the GPU is first used, so that the
-    worker processes are forked from a process without a GPU context."""
+def cpu_baseline_leg(f, cfg):
+    """The bench's oracle leg, the only part of it that touches the FP64
+    oracle.  Times the oracle on a bounded sample of the workload, on one
+    core and on every host core, and computes the oracle's reference values
+    for the accuracy statement: per sigma the oracle's own fit (T, c) and
+    eq. (1) with that cosine series at sampled pixels of the full image.
+    Runs before the GPU is first used, so that the worker processes are
+    forked from a process without a GPU context."""
     import numpy as np
 
     import oracle as O
+
+    rng = np.random.default_rng(77)
+    H, W = f.shape
+    ys = np.concatenate([rng.integers(0, H, 400), [0, 0, H - 1, H - 1, 17, H - 5]])
+    xs = np.concatenate([rng.integers(0, W, 400), [0, W - 1, 0, W - 1, W - 3, 9]])
+    refs = {"ys": ys, "xs": xs, "sigmas": {}}
+    for s in cfg.sigmas:
+        fit = O.fit(cfg.R, s, cfg.K)
+        want, _, _ = O.brute_bf_points(f, cfg.theta, O.cosine_series(fit["c"], fit["T"]),
+                                       ys, xs)
+        refs["sigmas"][s] = (fit["T"], np.asarray(fit["c"], dtype=np.float64), want)
 
     n = 2048
     crop = f[:n, :n]
@@ -558,30 +573,25 @@ def cpu_timing_leg(f, cfg):
                             "max_abs_vs_single_core": float(np.max(np.abs(par - serial)))}
     except Exception as e:  # reported, never hidden
         cpu["all_cores"] = {"error": repr(e)}
-    return cpu
+    return cpu, refs
 
 
-def accuracy_leg(f, cfg, modes, outs, step, F, torch):
-    """Each precision's max-abs and PSNR against the FP64 oracle's eq. (1)
-    with the same cosine series, on sampled pixels of the full image."""
+def accuracy_leg(img, cfg, modes, refs, F, torch):
+    """Each precision's max-abs and PSNR against the oracle's reference
+    values from the oracle leg (eq. (1) with the oracle's cosine series at
+    sampled pixels): the full image is filtered with the same (K, T, c)."""
     import numpy as np
 
-    import oracle as O
-
-    rng = np.random.default_rng(77)
-    H, W = f.shape
-    ys = np.concatenate([rng.integers(0, H, 400), [0, 0, H - 1, H - 1, 17, H - 5]])
-    xs = np.concatenate([rng.integers(0, W, 400), [0, W - 1, 0, W - 1, W - 3, 9]])
+    ys, xs = refs["ys"], refs["xs"]
+    out = torch.empty_like(img)
     acc = {}
     for m in modes:
-        step(m)
-        torch.cuda.synchronize()
         worst, se, cnt = 0.0, 0.0, 0
         for s in cfg.sigmas:
-            coef = F.fit(cfg.R, s, cfg.K, eps=cfg.eps)
-            got = outs[s].cpu().numpy()[ys, xs].astype(np.float64)
-            want, _, _ = O.brute_bf_points(f, cfg.theta,
-                                           O.cosine_series(coef.c, coef.T), ys, xs)
+            T, c, want = refs["sigmas"][s]
+            F.filter(img, cfg.theta, cfg.K, T, c, prec=m, out=out)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()[ys, xs].astype(np.float64)
             d = got - want
             worst = max(worst, float(np.max(np.abs(d))))
             se += float(np.sum(d * d))
