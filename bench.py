@@ -80,7 +80,7 @@ def write_trace_summary(stats_csv, bench_json):
     rows = list(csv.DictReader(open(stats_csv)))
     out = ["# Kernel trace: 4096^2 image, theta = 10 (61 taps), K = 8, "
            "sigma in {20, 50, 100}", "",
-           "Command (from the repository root on the GPU box; "
+           "Command (from the repository root on the MI355X host; "
            "`cd /tmp && export TMPDIR=/tmp` first):", "",
            "    rocprofv3 --kernel-trace --stats -d <out>/trace -o fobf "
            "--output-format csv -- \\",
@@ -248,7 +248,7 @@ def main():
         profile_run([m for m in args.modes.split(",") if m])
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; "
                           f"--gpus {args.gpus} is not supported"}))
         sys.exit(2)
 

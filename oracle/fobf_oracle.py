@@ -27,7 +27,7 @@ eye, in float64:
 * ``brute_bf_points``     eq. (1) at selected pixels, any range kernel.
 * ``psnr`` / ``max_abs``  the accuracy metric of Sec. III.
 
-Readings of points the paper leaves open (each one is listed in the design doc):
+Readings of points the paper leaves open:
 
 1. Period: frequencies are 2*pi*k/(2T+1) exactly as eq. (3) writes them.
 2. Window: square, radius r = ceil(3*theta); unnormalised taps,

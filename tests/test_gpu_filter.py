@@ -5,8 +5,10 @@ Tolerance: 0.5 intensity levels max-abs on pixels whose oracle denominator
 satisfies D(i)/W(i) >= 0.01 (where the cosine series keeps the
 denominator away from zero; D/W is the normalised denominator, 1 for the
 exact Gaussian kernel at a flat region).  Masked pixels are counted and
-reported.  FP32 results are additionally held to 0.05 levels, the bound
-derived in the design doc from float32 rounding of 29 channels x 61-tap sums.
+reported.  FP32 results are additionally held to 0.05 levels: each output
+is a ratio of sums over 29 channels x 61^2 taps of float32 products
+(relative rounding ~1e-5 accumulated), magnified by 1/(D/W) <= 100 on
+unmasked pixels and by |f| <= 255, about 0.03 in the worst case.
 """
 import math
 
