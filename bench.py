@@ -354,6 +354,9 @@ def main():
     roofline["measured_peak_tflops"] = measured
     if isinstance(measured.get("mfma_f32"), float):
         roofline["frac_of_measured_mfma_f32"] = round(achieved / measured["mfma_f32"], 4)
+    # the vector-ALU FMA rate code built without packed fp32 can issue
+    if isinstance(measured.get("valu_fma_f32"), float):
+        roofline["frac_of_measured_valu_fma_f32"] = round(achieved / measured["valu_fma_f32"], 4)
     print(f"[bench] measured peaks: {measured}", file=sys.stderr, flush=True)
 
     mixed = {}
