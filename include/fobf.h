@@ -48,7 +48,10 @@ typedef enum {
 
 typedef enum {
   FOBF_FP32 = 0,        /* channels and intermediates stored in float32     */
-  FOBF_FP16_STAGE = 1,  /* channels/intermediates staged in fp16, fp32 acc  */
+  FOBF_FP16_STAGE = 1,  /* channels/intermediates staged in fp16, fp32 acc.
+                           Error ~ 2^-9 sum|c_k| (local contrast) / (D/W):
+                           where a crude series (small K) leaves D/W small,
+                           use a two-word mode                              */
   FOBF_BF16_STAGE = 2,  /* staged as two bf16 words (hi + lo), fp32 acc      */
   FOBF_FP16X2_STAGE = 3 /* staged as two fp16 words (hi + lo), fp32 acc:
                            float32-class accuracy on the fp16 matrix cores  */

@@ -259,6 +259,41 @@ def test_c3_full_size_symmetries(algo, prec):
         assert math.isfinite(d) and d <= 2 * tol(prec), name
 
 
+def test_fp16_single_word_error_bound():
+    """A crude series (K = 2, sigma = 34: E = 12.6) leaves D/W as low as
+    0.013 on unmasked pixels.  There single-word fp16 staging cannot hold
+    0.5 levels: every staged value, tap and horizontal result is rounded to
+    fp16 (unit roundoff u = 2^-11), so V[X] is off by at most ~4u sum_j
+    w_j |X_j|, which the division by D amplifies by 1/(D/W).  With the
+    staged channels bounded by the image range (|f - m| <= range) this
+    gives, per pixel,
+
+        |out - exact| <= 5u sum_k |c_k| (2 range + |exact - f|) / (D/W)
+                         + (the float32 bound),
+
+    checked here on every unmasked pixel; the two-word modes and fp32 hold
+    their usual bounds on the same image."""
+    # the configuration of a seeded random sweep where fp16 was 4.1 levels off
+    H, W, theta, K, sigma = 436, 368, 3.02038299837791, 2, 34.0
+    f = workloads.voronoi_image(H, W, H * W // 300, True, 9083)
+    T, c = fitted(sigma, K)
+    ref, num, den = O.fourier_direct(f, theta, K, T, c, return_nd=True)
+    dw = den / O.blur_weight(H, W, theta)
+    mask = dw >= DMASK
+    u = 2.0 ** -11
+    span = float(f.max() - f.min())
+    bound = 5 * u * float(np.sum(np.abs(c[:K]))) * (2 * span + np.abs(ref - f)) / dw + TOL_F32
+    got = gpu_filter(f, theta, K, T, c, prec="fp16", algo="mfma")
+    err = np.abs(got - ref)
+    print("fp16 adversarial: min D/W", float(dw[mask].min()), "max err",
+          float(err[mask].max()), "max err / bound", float((err / bound)[mask].max()))
+    assert np.all(err[mask] <= bound[mask])
+    for prec in ("fp32", "bf16", "fp16x2"):
+        s = compare(f, theta, K, T, c, gpu_filter(f, theta, K, T, c, prec=prec, algo="mfma"))
+        print("adversarial", prec, s)
+        assert s["maxabs"] <= tol(prec)
+
+
 def test_filter_in_a_captured_graph():
     """fobf_filter enqueues kernels only (no allocation, no memset), so a
     caller can capture it in a HIP graph: three precisions captured once,
