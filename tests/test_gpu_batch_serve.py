@@ -98,6 +98,48 @@ def test_batch_mixed_precisions_and_edge_jobs():
     assert abs(float(tiny_out.cpu().numpy()[0, 0]) - 77.0) < 1e-3
 
 
+def test_batch_random_mixed():
+    """Seeded random batches (1..12 jobs, sizes up to 399^2, theta up to 16,
+    K up to 16, precisions mixed within a batch, pitched buffers): every
+    output against the oracle with the same (K, T, c), and nothing written
+    outside the output views."""
+    import torch
+    import paper_1811_02168_amd as F
+    precs = ["fp32", "fp16", "bf16", "fp16x2"]
+    tol = {"fp32": 0.05, "fp16x2": 0.05, "fp16": TOL, "bf16": TOL}
+    rng = np.random.default_rng(11)
+    for b in range(16):
+        n = int(rng.integers(1, 13))
+        descs, keep = [], []
+        for i in range(n):
+            H = int(rng.integers(1, 400))
+            W = int(rng.integers(1, 400))
+            theta = float(rng.uniform(0.3, 16.0))
+            K = int(rng.integers(1, 17))
+            sigma = float(round(rng.uniform(20, 120)))
+            prec = precs[int(rng.integers(0, 4))]
+            pad = int(rng.integers(0, 3))
+            f = workloads.voronoi_image(H, W, max(2, H * W // 300), bool(i % 2),
+                                        20000 + 100 * b + i)
+            fit = O.fit(255, sigma, K)
+            buf = torch.zeros((H, W + pad), dtype=torch.float32, device="cuda")
+            buf[:, :W] = torch.from_numpy(f.astype(np.float32))
+            obuf = torch.full((H, W + pad + 2), -777.0, dtype=torch.float32, device="cuda")
+            descs.append(F.make_job(buf[:, :W], obuf[:, :W], theta, K, fit["T"], fit["c"],
+                                    prec=prec))
+            keep.append((f, theta, K, fit["T"], fit["c"], prec, obuf, W))
+        F.filter_batch(descs)
+        torch.cuda.synchronize()
+        for f, theta, K, T, c, prec, obuf, W in keep:
+            o = obuf.cpu().numpy()
+            assert np.all(o[:, W:] == -777.0), ("write outside the output view", b)
+            ref, num, den = O.fourier_direct(f, theta, K, T, c, return_nd=True)
+            mask = den / O.blur_weight(*f.shape, theta) >= 0.01
+            err = float(np.max(np.abs(o[:, :W] - ref)[mask])) if mask.any() else 0.0
+            print("random batch", b, f.shape, round(theta, 2), K, prec, err)
+            assert err <= tol[prec], (b, f.shape, theta, K, prec, err)
+
+
 def test_batch_c4_workload_sample():
     """A slice of the 256-image uneven workload (sizes log-uniform 64^2 ..
     2048^2): every image equals its single-image launch."""

@@ -280,9 +280,7 @@ def test_fp16_single_word_error_bound():
     ref, num, den = O.fourier_direct(f, theta, K, T, c, return_nd=True)
     dw = den / O.blur_weight(H, W, theta)
     mask = dw >= DMASK
-    u = 2.0 ** -11
-    span = float(f.max() - f.min())
-    bound = 5 * u * float(np.sum(np.abs(c[:K]))) * (2 * span + np.abs(ref - f)) / dw + TOL_F32
+    bound = fp16_bound(f, K, c, ref, dw)
     got = gpu_filter(f, theta, K, T, c, prec="fp16", algo="mfma")
     err = np.abs(got - ref)
     print("fp16 adversarial: min D/W", float(dw[mask].min()), "max err",
@@ -292,6 +290,51 @@ def test_fp16_single_word_error_bound():
         s = compare(f, theta, K, T, c, gpu_filter(f, theta, K, T, c, prec=prec, algo="mfma"))
         print("adversarial", prec, s)
         assert s["maxabs"] <= tol(prec)
+
+
+def fp16_bound(f, K, c, ref, dw):
+    """Per-pixel error bound of single-word fp16 staging (derived in
+    test_fp16_single_word_error_bound)."""
+    u = 2.0 ** -11
+    span = float(f.max() - f.min())
+    return 5 * u * float(np.sum(np.abs(np.asarray(c)[:K]))) * (2 * span + np.abs(ref - f)) / dw \
+        + TOL_F32
+
+
+def test_random_configurations_wide():
+    """A wider seeded sweep: 100 random sizes up to 519^2, theta up to 16
+    (every radius class), K up to 32, sigma 8..150, integer and real-valued
+    images, pitched buffers and write-outside checks.  Every mode against
+    the oracle with the same (K, T, c); fp16 single-word staging against its
+    derived per-pixel bound (its fixed 0.5 bound fails where a crude series
+    leaves D/W small, as in case 83 here)."""
+    rng = np.random.default_rng(424242)
+    for case in range(100):
+        H = int(rng.integers(1, 520))
+        W = int(rng.integers(1, 520))
+        theta = float(rng.uniform(0.3, 16.0))
+        K = int(rng.integers(1, 33))
+        sigma = float(round(rng.uniform(8, 150)))
+        if case % 5 == 4:
+            f = rng.uniform(0, 255, size=(H, W))
+        else:
+            f = workloads.voronoi_image(H, W, max(2, H * W // 300), bool(case % 2), 9000 + case)
+        pad = int(rng.integers(0, 4))
+        T, c = fitted(sigma, K)
+        ref, num, den = O.fourier_direct(f, theta, K, T, c, return_nd=True)
+        dw = den / O.blur_weight(H, W, theta)
+        mask = dw >= DMASK
+        if not mask.any():
+            continue
+        for algo, prec in MODES:
+            got = gpu_filter(f, theta, K, T, c, prec=prec, algo=algo, pad=pad)
+            err = np.abs(got - ref)
+            print("wide", case, H, W, round(theta, 2), K, sigma, algo, prec,
+                  float(err[mask].max()))
+            if prec == "fp16":
+                assert np.all(err[mask] <= fp16_bound(f, K, c, ref, dw)[mask]), case
+            else:
+                assert float(err[mask].max()) <= tol(prec), (case, algo, prec)
 
 
 def test_filter_in_a_captured_graph():
