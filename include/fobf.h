@@ -285,12 +285,15 @@ fobf_status fobf_serve_create(const fobf_serve_cfg* cfg, fobf_server** out);
 fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req,
                               uint64_t* ticket);
 /* wait != 0 blocks until the request is done.  Returns the request's final
- * status (copied into *res too) or FOBF_EBUSY while it is pending. */
+ * status (copied into *res too) or FOBF_EBUSY while it is pending.  Once a
+ * final status has been returned the ticket is released: polling it again
+ * gives FOBF_EINVAL.  Thread-safe. */
 fobf_status fobf_serve_poll(fobf_server* s, uint64_t ticket, int wait,
                             fobf_result* res);
 /* Requests still queued when the server is destroyed complete with
  * FOBF_ECANCELED; work already on the device finishes first.  Tickets are
- * invalid afterwards. */
+ * invalid afterwards.  No other call on the same server may be running
+ * (a blocking poll must have returned) or start once destroy is called. */
 fobf_status fobf_serve_destroy(fobf_server* s);
 
 typedef struct {
