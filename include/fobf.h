@@ -189,6 +189,35 @@ fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W,
                         const double* c, int prec, int algo,
                         void* hip_stream);
 
+/*
+ * fobf_filter_workspace_size / fobf_filter_ws -- the same filter (Sec. II,
+ * first paragraph; outputs as fobf_filter, up to float32 summation order)
+ * with a caller-provided device workspace that holds each tile's running N
+ * and D instead of the LDS.  That frees the LDS for tiles of up to 512 rows,
+ * so far fewer of the vertical pass's halo rows are recomputed; the
+ * two-word modes (FOBF_BF16_STAGE, FOBF_FP16X2_STAGE) use it for images
+ * tall enough to give such tiles while still filling the device (e.g.
+ * 2048^2 and larger at theta <= 13.5).  For every other case the workspace
+ * is not used and fobf_filter_ws behaves exactly as fobf_filter.
+ *
+ * fobf_filter_workspace_size: *bytes = the workspace fobf_filter_ws needs
+ *   for an H x W image at this theta and precision (0: none; about 8 bytes
+ *   per pixel otherwise).  Host-only, no device work.  Validates H, W >= 0,
+ *   theta, prec and bytes != NULL (FOBF_EINVAL).
+ * fobf_filter_ws: arguments as fobf_filter, plus d_work (device memory, 4-
+ *   byte aligned, overlapping neither image) of work_bytes >=
+ *   fobf_filter_workspace_size; FOBF_EINVAL when it is needed and missing,
+ *   short, misaligned or overlapping.  The workspace needs no clearing
+ *   (every tile writes its N and D before reading them); it is scratch
+ *   owned by the caller, and two calls in flight at once need two
+ *   workspaces.  Enqueues kernels only (capturable), as fobf_filter.
+ */
+fobf_status fobf_filter_workspace_size(int H, int W, double theta, int prec, size_t* bytes);
+fobf_status fobf_filter_ws(const float* d_in, float* d_out, int H, int W, int ld_in,
+                           int ld_out, double theta, int K, int T, const double* c,
+                           int prec, int algo, void* d_work, size_t work_bytes,
+                           void* hip_stream);
+
 /* One image of a batch (all pointers device pointers, caller-owned). */
 typedef struct {
   const float* d_in;

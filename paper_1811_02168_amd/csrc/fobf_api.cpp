@@ -1,5 +1,6 @@
 // C ABI entry points: validation, parameter packing and dispatch.
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <string>
 
@@ -103,6 +104,53 @@ extern "C" fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W
   if (algo == FOBF_ALGO_AUTO) algo = (prec == FOBF_FP32) ? tc.algo : FOBF_ALGO_MFMA;
   if (algo == FOBF_ALGO_VALU) return launch_valu(p, hip_stream);
   return launch_mfma(p, prec, tc.nblk, hip_stream);
+}
+
+extern "C" fobf_status fobf_filter_workspace_size(int H, int W, double theta, int prec,
+                                                  size_t* bytes) {
+  if (!bytes) return fail(FOBF_EINVAL, "fobf_filter_workspace_size: bytes is NULL");
+  if (H < 0 || W < 0) return fail(FOBF_EINVAL, "fobf_filter_workspace_size: negative size");
+  const int r = spatial_radius(theta);
+  if (r < 1 || r > FOBF_RMAX)
+    return fail(FOBF_EINVAL, "fobf_filter_workspace_size: theta out of range");
+  if (prec < FOBF_FP32 || prec > FOBF_FP16X2_STAGE)
+    return fail(FOBF_EINVAL, "fobf_filter_workspace_size: unknown precision");
+  ImageParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.H = H;
+  p.W = W;
+  p.r = r;
+  *bytes = ws_bytes(p, prec);
+  return FOBF_OK;
+}
+
+extern "C" fobf_status fobf_filter_ws(const float* d_in, float* d_out, int H, int W,
+                                      int ld_in, int ld_out, double theta, int K, int T,
+                                      const double* c, int prec, int algo, void* d_work,
+                                      size_t work_bytes, void* hip_stream) {
+  fobf_status st = validate_filter(d_in, d_out, H, W, ld_in, ld_out, theta, K, T, c, prec, algo);
+  if (st != FOBF_OK) return st;
+  if (H == 0 || W == 0) return FOBF_OK;
+  ImageParams p;
+  make_params(p, d_in, d_out, H, W, ld_in, ld_out, theta, K, T, c);
+  const size_t need = ws_bytes(p, prec);
+  if (need == 0 || algo == FOBF_ALGO_VALU)
+    return fobf_filter(d_in, d_out, H, W, ld_in, ld_out, theta, K, T, c, prec, algo,
+                       hip_stream);
+  if (!d_work || work_bytes < need)
+    return fail(FOBF_EINVAL, "fobf_filter_ws: workspace missing or below "
+                             "fobf_filter_workspace_size");
+  if (reinterpret_cast<uintptr_t>(d_work) % alignof(float) != 0)
+    return fail(FOBF_EINVAL, "fobf_filter_ws: workspace not 4-byte aligned");
+  const char* w0 = static_cast<const char*>(d_work);
+  const char* w1 = w0 + need;
+  const char* a0 = reinterpret_cast<const char*>(d_in);
+  const char* a1 = a0 + sizeof(float) * ((static_cast<size_t>(H) - 1) * ld_in + W);
+  const char* b0 = reinterpret_cast<const char*>(d_out);
+  const char* b1 = b0 + sizeof(float) * ((static_cast<size_t>(H) - 1) * ld_out + W);
+  if ((w0 < a1 && a0 < w1) || (w0 < b1 && b0 < w1))
+    return fail(FOBF_EINVAL, "fobf_filter_ws: workspace overlaps an image");
+  return launch_mfma_ws(p, prec, static_cast<float*>(d_work), hip_stream);
 }
 
 extern "C" const char* fobf_last_error(void) { return fobf::error_cstr(); }

@@ -52,6 +52,11 @@ fobf_status validate_filter(const float* in, const float* out, int H, int W,
 // message set.
 fobf_status launch_valu(const ImageParams& p, void* stream);
 fobf_status launch_mfma(const ImageParams& p, int prec, int nblk, void* stream);
+// Workspace form (fobf_filter_ws): tile height in 16-row blocks (0: not
+// used for this image and precision), workspace bytes it needs, launch.
+int ws_nblk(const ImageParams& p, int prec);
+size_t ws_bytes(const ImageParams& p, int prec);
+fobf_status launch_mfma_ws(const ImageParams& p, int prec, float* work, void* stream);
 
 // Tuning table (fobf_tune.cpp): per precision and radius class dv =
 // ceil((16 + 2r) / 16), the algorithm and tile height chosen by

@@ -9,6 +9,9 @@
 #include "fobf_tiles.h"
 
 namespace fobf {
+
+constexpr int kWsWaves = 8;   // strips per workgroup of the workspace form
+
 namespace {
 
 template <int SH>
@@ -56,6 +59,27 @@ __global__ __launch_bounds__((64 * staged_waves<OT, DV>())) void mfma_staged_ker
   const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
   __syncthreads();
   staged_tile<OT, DV, NW>(im, tx, ty, nblk, tbl, sbuf, nd);
+}
+
+// Tall-tile form of the staged kernel: each tile's N and D live in a global
+// workspace (2 nblk 256 floats per wave, tiles in row-major order), so the
+// LDS holds only the staging buffer and the tile can be 512 rows tall.
+template <typename OT, int DV>
+__global__ __launch_bounds__((64 * staged_waves<OT, DV>())) void mfma_staged_ws_kernel(
+    ImageParams p, int nblk, float* work) {
+  constexpr int NW = staged_waves<OT, DV>();
+  extern __shared__ float lds[];
+  const int ntx = (p.W + NW * MSTRIP - 1) / (NW * MSTRIP);
+  const int nty = (p.H + 16 * nblk - 1) / (16 * nblk);
+  int tx, ty;
+  if (!tile_of_block(blockIdx.x, gridDim.x, ntx, nty, &tx, &ty)) return;
+  float* tbl = lds;
+  typename Stage<OT>::T* sbuf = reinterpret_cast<typename Stage<OT>::T*>(lds + LDS_TABLE);
+  float* nd = work + (static_cast<size_t>(ty) * ntx + tx) * (NW * 2 * 256) * nblk;
+  FOBF_LOAD_TABLES(p, tbl);
+  const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
+  __syncthreads();
+  staged_tile<OT, DV, NW, true>(im, tx, ty, nblk, tbl, sbuf, nd);
 }
 
 // ------------------------------------------------------------------ host --
@@ -130,7 +154,65 @@ fobf_status launch_staged(const ImageParams& p, int DV, int nblk, void* stream) 
   }
 }
 
+template <typename OT, int DV>
+fobf_status launch_staged_ws_dv(const ImageParams& p, int nblk, float* work, void* stream) {
+  static const bool once = (allow_big_lds(mfma_staged_ws_kernel<OT, DV>), true);
+  (void)once;
+  constexpr int NW = staged_waves<OT, DV>();
+  static_assert(NW == kWsWaves, "the workspace form runs eight strips");
+  const size_t lds = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV, NW>();
+  dim3 grid(padded_blocks(p, nblk, NW));
+  hipLaunchKernelGGL((mfma_staged_ws_kernel<OT, DV>), grid, dim3(64 * NW), lds,
+                     static_cast<hipStream_t>(stream), p, nblk, work);
+  return check_launch("mfma_staged_ws_kernel");
+}
+
+template <typename OT>
+fobf_status launch_staged_ws(const ImageParams& p, int DV, int nblk, float* work,
+                             void* stream) {
+  switch (DV) {
+    case 2: return launch_staged_ws_dv<OT, 2>(p, nblk, work, stream);
+    case 3: return launch_staged_ws_dv<OT, 3>(p, nblk, work, stream);
+    case 4: return launch_staged_ws_dv<OT, 4>(p, nblk, work, stream);
+    case 5: return launch_staged_ws_dv<OT, 5>(p, nblk, work, stream);
+    case 6: return launch_staged_ws_dv<OT, 6>(p, nblk, work, stream);
+    default: return fail(FOBF_EINTERNAL, "fobf_filter_ws: no workspace form for this radius");
+  }
+}
+
 }  // namespace
+
+// Tile height (16-row blocks) of the workspace form, or 0 where it is not
+// used: only the two-word modes (whose LDS otherwise caps tiles at 96 rows)
+// at radius classes DV = 2..6 (eight strips), and only when the image is
+// tall enough for tiles of at least 8 blocks while still giving about one
+// workgroup per compute unit (256 on the MI355X).  At most 32 blocks.
+int ws_nblk(const ImageParams& p, int prec) {
+  if (prec != FOBF_BF16_STAGE && prec != FOBF_FP16X2_STAGE) return 0;
+  const int DV = (MSTRIP + 2 * p.r + 15) / 16;
+  if (DV < 2 || DV > 6 || p.H < 1 || p.W < 1) return 0;
+  const long ntx = (p.W + kWsWaves * MSTRIP - 1) / (kWsWaves * MSTRIP);
+  const long rows = (p.H + 15) / 16;
+  const long nty_target = (256 + ntx - 1) / ntx;
+  const long nblk = std::min<long>(32, (rows + nty_target - 1) / nty_target);
+  return nblk >= 8 ? static_cast<int>(nblk) : 0;
+}
+
+size_t ws_bytes(const ImageParams& p, int prec) {
+  const int nblk = ws_nblk(p, prec);
+  if (nblk == 0) return 0;
+  const size_t ntx = (p.W + kWsWaves * MSTRIP - 1) / (kWsWaves * MSTRIP);
+  const size_t nty = (p.H + 16 * nblk - 1) / (16 * nblk);
+  return sizeof(float) * ntx * nty * kWsWaves * 2 * 256 * static_cast<size_t>(nblk);
+}
+
+fobf_status launch_mfma_ws(const ImageParams& p, int prec, float* work, void* stream) {
+  const int nblk = ws_nblk(p, prec);
+  const int DV = (MSTRIP + 2 * p.r + 15) / 16;
+  if (nblk == 0) return fail(FOBF_EINTERNAL, "fobf_filter_ws: no workspace form");
+  if (prec == FOBF_BF16_STAGE) return launch_staged_ws<__bf16>(p, DV, nblk, work, stream);
+  return launch_staged_ws<F16Pair>(p, DV, nblk, work, stream);
+}
 
 fobf_status launch_mfma(const ImageParams& p, int prec, int nblk, void* stream) {
   const int DV = (MSTRIP + 2 * p.r + 15) / 16;

@@ -48,6 +48,9 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bh4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
 
 constexpr int MWAVES = 4;             // waves per workgroup = x strips
 constexpr int MTHREADS = 64 * MWAVES;
@@ -385,6 +388,10 @@ struct Stage<_Float16> {
   __device__ static __forceinline__ f4 mfma(v8 a, v8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
+  // K = 16 product: one horizontal block (4 words per lane) per operand
+  __device__ static __forceinline__ f4 mfma16(h4 a, h4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
   __device__ static __forceinline__ _Float16 cvt(float x) { return static_cast<_Float16>(x); }
   // two staged values as one 32-bit word (round to nearest)
   __device__ static __forceinline__ void pack2(float x0, float x1, uint32_t (&w)[1]) {
@@ -407,6 +414,10 @@ struct Stage<__bf16> {
   static constexpr int kParts = 2;
   __device__ static __forceinline__ f4 mfma(v8 a, v8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ f4 mfma16(bh4 a, bh4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a),
+                                                     __builtin_bit_cast(s4, b), c, 0, 0, 0);
   }
   __device__ static __forceinline__ __bf16 cvt(float x) { return static_cast<__bf16>(x); }
   // two staged values as hi and lo words.  For the staged channels hi is
@@ -440,6 +451,9 @@ struct Stage<F16Pair> {
   static constexpr int kParts = 2;
   __device__ static __forceinline__ f4 mfma(v8 a, v8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ f4 mfma16(h4 a, h4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
   }
   __device__ static __forceinline__ _Float16 cvt(float x) { return static_cast<_Float16>(x); }
   __device__ static __forceinline__ void pack2(float x0, float x1, uint32_t (&w)[2]) {
@@ -585,7 +599,14 @@ __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shi
     }
 }
 
-template <typename OT, int DV, int G, int NW>
+// GND = false: N and D of the tile live in LDS (the single-image and batch
+// kernels).  GND = true: they live in a global workspace, which frees the
+// LDS for much taller tiles (fewer halo blocks per output block); the
+// block's N and D are then fetched at the head of the block, a whole block
+// of matrix work ahead of the fold, and the vertical pass uses the K = 16
+// product (one horizontal block per operand: no register moves to pair
+// blocks, fewer registers).
+template <typename OT, int DV, int G, int NW, bool GND = false>
 __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, int x0, int y0,
                                              int nblk, const float* tbl,
                                              typename Stage<OT>::T* sbuf, float* Ns,
@@ -626,25 +647,48 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   // (elements 4..7); element j <-> H row 16 (2t + j/4) + 4 lk + j%4
   // (two-word modes: built by wave 0 into the LDS table after the staging
   // buffers and read back per vertical step)
+  // (K = 16 form, GND: one operand per H block d, element j <-> H row
+  // 16 d + 4 lk + j; the table fits in the same LDS bytes)
   constexpr bool kVtapLds = staged_vtap_in_lds<OT, NW>();
-  v8 Aw[NV][NS];
+  static_assert(!GND || !kVtapLds ||
+                    DV * NS * 64 * sizeof(o4) <= staged_vtap_bytes<OT, DV, NW>(),
+                "the K = 16 tap table must fit the vertical tap area");
+  v8 Aw[GND ? 1 : NV][NS];
+  o4 Aw4[GND ? DV : 1][NS];
   v8* const vtap = reinterpret_cast<v8*>(reinterpret_cast<char*>(sbuf) +
                                          staged_stage_bytes<OT, DV, NW>());
+  o4* const vtap4 = reinterpret_cast<o4*>(vtap);
   if (!kVtapLds || wave == 0) {
+    if constexpr (GND) {
 #pragma unroll
-    for (int t = 0; t < NV; ++t)
+      for (int d = 0; d < DV; ++d)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int blk = 2 * t + (j >> 2);
-        const float w = blk < DV ? tap(gS, 16 * blk + 4 * lk + (j & 3) - r - li, r) : 0.f;
-        Aw[t][0][j] = S::cvt(w);
-        if (NS == 2) Aw[t][NS - 1][j] = S::cvt(w - static_cast<float>(Aw[t][0][j]));
-      }
-    if (kVtapLds)
+        for (int j = 0; j < 4; ++j) {
+          const float w = tap(gS, 16 * d + 4 * lk + j - r - li, r);
+          Aw4[d][0][j] = S::cvt(w);
+          if (NS == 2) Aw4[d][NS - 1][j] = S::cvt(w - static_cast<float>(Aw4[d][0][j]));
+        }
+      if (kVtapLds)
+#pragma unroll
+        for (int d = 0; d < DV; ++d)
+#pragma unroll
+          for (int h = 0; h < NS; ++h) vtap4[(d * NS + h) * 64 + lane] = Aw4[d][h];
+    } else {
 #pragma unroll
       for (int t = 0; t < NV; ++t)
 #pragma unroll
-        for (int h = 0; h < NS; ++h) vtap[(t * NS + h) * 64 + lane] = Aw[t][h];
+        for (int j = 0; j < 8; ++j) {
+          const int blk = 2 * t + (j >> 2);
+          const float w = blk < DV ? tap(gS, 16 * blk + 4 * lk + (j & 3) - r - li, r) : 0.f;
+          Aw[t][0][j] = S::cvt(w);
+          if (NS == 2) Aw[t][NS - 1][j] = S::cvt(w - static_cast<float>(Aw[t][0][j]));
+        }
+      if (kVtapLds)
+#pragma unroll
+        for (int t = 0; t < NV; ++t)
+#pragma unroll
+          for (int h = 0; h < NS; ++h) vtap[(t * NS + h) * 64 + lane] = Aw[t][h];
+    }
   }
 
   o4 ring[DV][NS][G];
@@ -665,6 +709,14 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
         // staging so that they arrive during the block's matrix work (rows
         // clamped: blocks with pb < 0 fold nothing)
         float fo[4];
+        float nv[4], dv[4];
+        if (GND && pb >= 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            nv[v] = Ns[pb * 256 + 64 * v + lane];
+            if (G == 4) dv[v] = Ds[pb * 256 + 64 * v + lane];
+          }
+        }
         if (G == 4) {
           const int gx = min(x0w + li, im.W - 1);
 #pragma unroll
@@ -717,6 +769,23 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
           f4 vacc[G];
 #pragma unroll
           for (int g = 0; g < G; ++g) vacc[g] = f4{0.f, 0.f, 0.f, 0.f};
+          if constexpr (GND) {
+#pragma unroll
+            for (int d = 0; d < DV; ++d) {
+              const int slot = (u + 1 + d) % DV;
+              o4 aw[NS];
+#pragma unroll
+              for (int h = 0; h < NS; ++h)
+                aw[h] = kVtapLds ? vtap4[(d * NS + h) * 64 + lane] : Aw4[d][h];
+#pragma unroll
+              for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int ha = 0; ha < NS; ++ha)
+#pragma unroll
+                  for (int hb = 0; hb + ha < NS; ++hb)
+                    vacc[g] = S::mfma16(aw[ha], ring[slot][hb][g], vacc[g]);
+            }
+          } else {
 #pragma unroll
           for (int t = 0; t < NV; ++t) {
             const int b0 = 2 * t, b1 = (2 * t + 1 < DV) ? 2 * t + 1 : 2 * t;
@@ -738,14 +807,16 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
                 for (int hb = 0; hb + ha < NS; ++hb) vacc[g] = S::mfma(aw[ha], b[hb], vacc[g]);
             }
           }
+          }
           // fold (all reads of N, D before the writes they may alias)
           float* const nrow = Ns + pb * 256 + lane;
           float* const drow = Ds + pb * 256 + lane;
-          float nv[4], dv[4];
+          if (!GND) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            nv[v] = nrow[64 * v];
-            if (G == 4) dv[v] = drow[64 * v];
+            for (int v = 0; v < 4; ++v) {
+              nv[v] = nrow[64 * v];
+              if (G == 4) dv[v] = drow[64 * v];
+            }
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -769,7 +840,9 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   }
 }
 
-template <typename OT, int DV, int NW>
+// nd: N and D of the tile's waves, 2 * nblk * 256 floats per wave (in LDS,
+// or for GND this workgroup's share of the global workspace).
+template <typename OT, int DV, int NW, bool GND = false>
 __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int nblk,
                                             const float* tbl, typename Stage<OT>::T* sbuf,
                                             float* nd) {
@@ -794,9 +867,9 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
   const float shift = im.in[static_cast<size_t>(min(y0 + TYo / 2, im.H - 1)) * im.ld_in +
                             min(x0 + NW * MSTRIP / 2, im.W - 1)];
   init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);
-  staged_group<OT, DV, 1, NW>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+  staged_group<OT, DV, 1, NW, GND>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
   for (int k = 1; k < im.K; ++k)
-    staged_group<OT, DV, 4, NW>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+    staged_group<OT, DV, 4, NW, GND>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
   store_nd(im, x0w, y0, nblk, Ns, Ds, lane, shift);
 }
 

@@ -37,6 +37,7 @@ EXPORTS = [
     "fobf_serve_get_stats", "fobf_serve_inject_fault", "fobf_last_error",
     "fobf_version", "fobf_peak", "fobf_fit_period", "fobf_lut_create", "fobf_lut_get",
     "fobf_lut_fit", "fobf_lut_save", "fobf_lut_load", "fobf_lut_destroy",
+    "fobf_filter_workspace_size", "fobf_filter_ws",
 ]
 
 
@@ -105,6 +106,11 @@ def _load():
             fn.restype = restype
 
     bind("fobf_batch_workspace_size", [C.c_int], C.c_size_t)
+    bind("fobf_filter_workspace_size", [C.c_int, C.c_int, C.c_double, C.c_int,
+                                        C.POINTER(C.c_size_t)])
+    bind("fobf_filter_ws", [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                            C.c_double, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
+                            C.c_int, C.c_void_p, C.c_size_t, C.c_void_p])
     bind("fobf_filter_batch", [C.POINTER(_Job), C.c_int, C.c_void_p,
                                C.c_size_t, C.c_void_p])
     bind("fobf_serve_create", [C.POINTER(_ServeCfg), C.POINTER(C.c_void_p)])
@@ -299,10 +305,21 @@ def _check_image(t, name):
         raise TypeError(f"{name} must be 2-D float32 with unit column stride")
 
 
+def filter_workspace_size(H: int, W: int, theta: float, prec="fp32") -> int:
+    """fobf_filter_workspace_size: bytes of device workspace filter(...,
+    workspace=...) uses for this image (0: none)."""
+    n = C.c_size_t()
+    _check(lib.fobf_filter_workspace_size(int(H), int(W), float(theta), _prec(prec),
+                                          C.byref(n)))
+    return n.value
+
+
 def filter(img, theta: float, K: int, T: int, c, prec="fp32", algo="auto",
-           out=None, stream=None):
+           out=None, stream=None, workspace=None):
     """fobf_filter on a 2-D float32 CUDA tensor; returns the output tensor.
-    Enqueued on ``stream`` (default: torch's current stream)."""
+    Enqueued on ``stream`` (default: torch's current stream).  With
+    ``workspace`` (a CUDA tensor of at least filter_workspace_size bytes)
+    the call goes to fobf_filter_ws."""
     import torch
     _check_image(img, "img")
     H, W = img.shape
@@ -312,10 +329,20 @@ def filter(img, theta: float, K: int, T: int, c, prec="fp32", algo="auto",
     if tuple(out.shape) != (H, W):
         raise ValueError("out shape mismatch")
     carr = _carr(c, K)
-    st = lib.fobf_filter(C.c_void_p(img.data_ptr()), C.c_void_p(out.data_ptr()),
-                         H, W, img.stride(0), out.stride(0), float(theta),
-                         int(K), int(T), carr, _prec(prec), _algo(algo),
-                         _stream_ptr(stream))
+    if workspace is None:
+        st = lib.fobf_filter(C.c_void_p(img.data_ptr()), C.c_void_p(out.data_ptr()),
+                             H, W, img.stride(0), out.stride(0), float(theta),
+                             int(K), int(T), carr, _prec(prec), _algo(algo),
+                             _stream_ptr(stream))
+    else:
+        if not workspace.is_cuda:
+            raise ValueError("workspace must be a CUDA tensor")
+        nbytes = workspace.numel() * workspace.element_size()
+        st = lib.fobf_filter_ws(C.c_void_p(img.data_ptr()), C.c_void_p(out.data_ptr()),
+                                H, W, img.stride(0), out.stride(0), float(theta),
+                                int(K), int(T), carr, _prec(prec), _algo(algo),
+                                C.c_void_p(workspace.data_ptr()), nbytes,
+                                _stream_ptr(stream))
     _check(st)
     return out
 

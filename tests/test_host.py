@@ -120,6 +120,52 @@ def test_fit_invalid_arguments():
         F.fit(255, 30.0, 4, eps=0.0)
 
 
+def test_filter_workspace_without_device():
+    """fobf_filter_workspace_size is host arithmetic: zero where the
+    workspace form is not used (fp32, single fp16, small images, the
+    largest radius class), 8 bytes per pixel of whole tiles otherwise; and
+    fobf_filter_ws rejects bad arguments and a missing, short, misaligned or
+    overlapping workspace on the host, before any HIP call."""
+    import ctypes as C
+    import paper_1811_02168_amd as F
+    size = F.filter_workspace_size
+    for prec in ("fp32", "fp16"):
+        assert size(4096, 4096, 10.0, prec) == 0
+    for prec in ("bf16", "fp16x2"):
+        assert size(1024, 1024, 10.0, prec) == 0            # tiles would be short
+        assert size(4096, 4096, 15.0, prec) == 0            # radius class DV = 7
+        assert size(4096, 4096, 10.0, prec) == 8 * 4096 * 4096
+        assert size(2048, 2048, 5.0, prec) == 8 * 2048 * 2048
+        assert size(0, 4096, 10.0, prec) == 0
+        n = size(3000, 2500, 10.0, prec)                    # ragged: whole tiles
+        assert n >= 8 * 3000 * 2500 and n % (8 * 128 * 16) == 0
+    lib = F.lib
+    n = C.c_size_t()
+    for args in [(-1, 4, 1.0, 2), (4, 4, 0.0, 2), (4, 4, 17.0, 2), (4, 4, 1.0, 9)]:
+        assert lib.fobf_filter_workspace_size(*args, C.byref(n)) == F.fobf.EINVAL
+    assert lib.fobf_filter_workspace_size(4, 4, 1.0, 2, None) == F.fobf.EINVAL
+    c = (C.c_double * 32)(*([0.5, 0.5] + [0.0] * 30))
+    H = W = 4096
+    need = size(H, W, 10.0, "fp16x2")
+    fake_in, fake_out = C.c_void_p(0x100000000), C.c_void_p(0x200000000)
+    ws = C.c_void_p(0x300000000)
+    bad = [
+        (fake_in, fake_out, H, W, W, W, 10.0, 2, 5, c, 3, 0, None, need),        # no workspace
+        (fake_in, fake_out, H, W, W, W, 10.0, 2, 5, c, 3, 0, ws, need - 1),      # short
+        (fake_in, fake_out, H, W, W, W, 10.0, 2, 5, c, 3, 0,
+         C.c_void_p(0x300000002), need),                                        # misaligned
+        (fake_in, fake_out, H, W, W, W, 10.0, 2, 5, c, 3, 0,
+         C.c_void_p(0x100000000 + 4096), need),                                 # overlaps input
+        (fake_in, fake_out, H, W, W, W, 10.0, 2, 5, c, 3, 0,
+         C.c_void_p(0x200000000 - 16), need),                                   # overlaps output
+        (fake_in, fake_out, H, W, W, W, 10.0, 0, 5, c, 3, 0, ws, need),          # K = 0
+        (None, fake_out, H, W, W, W, 10.0, 2, 5, c, 3, 0, ws, need),             # null input
+    ]
+    for a in bad:
+        assert lib.fobf_filter_ws(*a, None) == F.fobf.EINVAL, (a, F.last_error())
+        assert F.last_error()
+
+
 def test_filter_validation_without_device():
     """Invalid arguments are rejected on the host, before any HIP call."""
     import ctypes as C
