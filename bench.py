@@ -46,7 +46,8 @@ def parse():
                     help="timed requests of the warm-cache serving leg (after "
                     "a tenth as many warm-up requests); the cold-cache leg "
                     "times a quarter as many")
-    ap.add_argument("--modes", default="fp32,fp16,bf16,fp16x2")
+    ap.add_argument("--modes", default="fp32,fp16,bf16,fp16x2,bf16_ws,fp16x2_ws",
+                    help="precisions; a _ws suffix calls fobf_filter_ws with a workspace")
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3 counter passes: one 256 MiB device "
                     "copy (calibrates FETCH_SIZE/WRITE_SIZE), then one launch "
@@ -67,7 +68,24 @@ KERNEL_LABELS = {
     "mfma_staged_f16_c3": "fp16-staged (16x16x32 f16, fp32 accumulation)",
     "mfma_staged_bf16_c3": "bf16 hi+lo staged (16x16x32 bf16, fp32 accumulation)",
     "mfma_staged_f16x2_c3": "fp16 hi+lo staged (16x16x32 f16, fp32 accumulation)",
+    "mfma_staged_ws_bf16_c3": "bf16 hi+lo staged, workspace form (512-row tiles)",
+    "mfma_staged_ws_f16x2_c3": "fp16 hi+lo staged, workspace form (512-row tiles)",
 }
+
+
+MODE_TRAFFIC = {"fp16": "mfma_staged_f16_c3", "bf16": "mfma_staged_bf16_c3",
+                "fp16x2": "mfma_staged_f16x2_c3", "bf16_ws": "mfma_staged_ws_bf16_c3",
+                "fp16x2_ws": "mfma_staged_ws_f16x2_c3"}
+
+
+def mode_call(m, H, W, theta, torch):
+    """(precision, workspace tensor or None) of a bench mode name."""
+    import paper_1811_02168_amd as F
+    if not m.endswith("_ws"):
+        return m, None
+    prec = m[:-3]
+    n = F.filter_workspace_size(H, W, theta, prec)
+    return prec, torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
 
 
 def write_trace_summary(stats_csv, bench_json):
@@ -125,7 +143,8 @@ def profile_run(modes):
     out = torch.empty_like(img)
     coef = F.fit(cfg.R, 50.0, cfg.K, eps=cfg.eps)
     for m in modes:
-        F.filter(img, cfg.theta, cfg.K, coef.T, coef.c, prec=m, out=out)
+        prec, ws = mode_call(m, cfg.H, cfg.W, cfg.theta, torch)
+        F.filter(img, cfg.theta, cfg.K, coef.T, coef.c, prec=prec, out=out, workspace=ws)
         torch.cuda.synchronize()
         print(f"[profile-run] {m} done", file=sys.stderr, flush=True)
 
@@ -151,6 +170,10 @@ TRAFFIC_KERNELS = {            # key -> substrings naming the kernel
     "mfma_staged_bf16_c3": ("mfma_staged_kernel<__bf16, 5>", "mfma_staged_kernelIDF16bLi5E"),
     "mfma_staged_f16x2_c3": ("mfma_staged_kernel<fobf::(anonymous namespace)::F16Pair, 5>",
                              "mfma_staged_kernelINS0_7F16PairELi5E"),
+    "mfma_staged_ws_bf16_c3": ("mfma_staged_ws_kernel<__bf16, 5>",
+                               "mfma_staged_ws_kernelIDF16bLi5E"),
+    "mfma_staged_ws_f16x2_c3": ("mfma_staged_ws_kernel<fobf::(anonymous namespace)::F16Pair, 5>",
+                                "mfma_staged_ws_kernelINS0_7F16PairELi5E"),
 }
 
 
@@ -274,10 +297,15 @@ def main():
     outs = {s: torch.empty_like(img) for s in cfg.sigmas}
     stream = torch.cuda.current_stream()
 
-    def step(prec):
+    calls = {}
+
+    def step(mode):
+        if mode not in calls:
+            calls[mode] = mode_call(mode, H, W, theta, torch)
+        prec, ws = calls[mode]
         for s in cfg.sigmas:
             coef = F.fit(R, s, K, eps=cfg.eps)         # cached host fit
-            F.filter(img, theta, K, coef.T, coef.c, prec=prec, out=outs[s])
+            F.filter(img, theta, K, coef.T, coef.c, prec=prec, out=outs[s], workspace=ws)
 
     def timed(prec, steps, warmup):
         for _ in range(warmup):
@@ -369,7 +397,8 @@ def main():
             "ms_per_step": round(res[m]["ms_per_step"], 4),
             "kernel_ms": round(res[m]["kernel_ms"], 4),
             "tflops_equiv": round(a, 2),
-            "frac_fp32_peak": round(a / PEAK_FP32_TFLOPS, 4)}
+            "frac_fp32_peak": round(a / PEAK_FP32_TFLOPS, 4),
+            "hbm_bytes_per_launch": traffic_record(MODE_TRAFFIC.get(m, ""), alg_bytes)}
 
     accuracy = None
     if not args.no_cpu_baseline:
@@ -592,7 +621,8 @@ def accuracy_leg(img, cfg, modes, refs, F, torch):
         worst, se, cnt = 0.0, 0.0, 0
         for s in cfg.sigmas:
             T, c, want = refs["sigmas"][s]
-            F.filter(img, cfg.theta, cfg.K, T, c, prec=m, out=out)
+            prec, ws = mode_call(m, cfg.H, cfg.W, cfg.theta, torch)
+            F.filter(img, cfg.theta, cfg.K, T, c, prec=prec, out=out, workspace=ws)
             torch.cuda.synchronize()
             got = out.cpu().numpy()[ys, xs].astype(np.float64)
             d = got - want
