@@ -160,7 +160,8 @@ fobf_status launch_staged_ws_dv(const ImageParams& p, int nblk, float* work, voi
   (void)once;
   constexpr int NW = staged_waves<OT, DV>();
   static_assert(NW == kWsWaves, "the workspace form runs eight strips");
-  const size_t lds = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV, NW>();
+  constexpr size_t lds = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV, NW, true>();
+  static_assert(lds <= 160 * 1024, "staging buffers exceed the LDS");
   dim3 grid(padded_blocks(p, nblk, NW));
   hipLaunchKernelGGL((mfma_staged_ws_kernel<OT, DV>), grid, dim3(64 * NW), lds,
                      static_cast<hipStream_t>(stream), p, nblk, work);

@@ -496,19 +496,21 @@ constexpr int stage_width() {
 // one before it is still being read (one barrier per block); one buffer
 // costs a second barrier per block but halves the staging LDS, which pays
 // for taller tiles (less vertical halo) and wider workgroups: measured at
-// 4096^2, r = 30, fp16 0.75 -> 0.62 ms and bf16 1.61 -> 1.28 ms.
-template <typename OT, int NW>
-constexpr int staged_bufs() { return 1; }
+// 4096^2, r = 30, fp16 0.75 -> 0.62 ms and bf16 1.61 -> 1.28 ms.  The
+// workspace form (GND: N and D outside the LDS) has the room for two, and
+// there they save 1-3%.
+template <typename OT, int NW, bool GND = false>
+constexpr int staged_bufs() { return GND ? 2 : 1; }
 
 // The staging region: the channel buffers, then (two-word modes at eight
 // strips only) the per-lane vertical Toeplitz slices, which would otherwise
 // hold 24 VGPRs per lane through the whole group at the kernel's register
 // limit.  Four-strip workgroups (the batch kernel) keep them in registers:
 // there the LDS is worth more as tile height.
-template <typename OT, int DV, int NW>
+template <typename OT, int DV, int NW, bool GND = false>
 constexpr size_t staged_stage_bytes() {
-  return sizeof(typename Stage<OT>::T) * staged_bufs<OT, NW>() * Stage<OT>::kParts * STAGE_CH * 16 *
-         stage_pitch(stage_width<DV, NW>());
+  return sizeof(typename Stage<OT>::T) * staged_bufs<OT, NW, GND>() * Stage<OT>::kParts *
+         STAGE_CH * 16 * stage_pitch(stage_width<DV, NW>());
 }
 
 template <typename OT, int NW>
@@ -519,9 +521,9 @@ constexpr size_t staged_vtap_bytes() {
   return staged_vtap_in_lds<OT, NW>() ? static_cast<size_t>((DV + 1) / 2) * 2 * 64 * 16 : 0;
 }
 
-template <typename OT, int DV, int NW>
+template <typename OT, int DV, int NW, bool GND = false>
 constexpr size_t staged_buf_bytes() {
-  return staged_stage_bytes<OT, DV, NW>() + staged_vtap_bytes<OT, DV, NW>();
+  return staged_stage_bytes<OT, DV, NW, GND>() + staged_vtap_bytes<OT, DV, NW>();
 }
 
 // Issues the global loads of this thread's item of one block into
@@ -656,7 +658,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   v8 Aw[GND ? 1 : NV][NS];
   o4 Aw4[GND ? DV : 1][NS];
   v8* const vtap = reinterpret_cast<v8*>(reinterpret_cast<char*>(sbuf) +
-                                         staged_stage_bytes<OT, DV, NW>());
+                                         staged_stage_bytes<OT, DV, NW, GND>());
   o4* const vtap4 = reinterpret_cast<o4*>(vtap);
   if (!kVtapLds || wave == 0) {
     if constexpr (GND) {
@@ -701,7 +703,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
     for (int u = 0; u < DV; ++u) {
       const int q = qq + u;
       if (q < QB) {
-        constexpr int NBUF = staged_bufs<OT, NW>();
+        constexpr int NBUF = staged_bufs<OT, NW, GND>();
         typename S::T* buf = sbuf + (NBUF == 2 ? (q & 1) : 0) * (NS * STAGE_CH * 16 * PC);
         const int row0 = y0 - r + 16 * q;
         const int pb = q - (DV - 1);
@@ -858,7 +860,7 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
   // by zero taps and are never written, so they must hold finite values
   {
     float4* z = reinterpret_cast<float4*>(sbuf);
-    const int n16 = static_cast<int>(staged_stage_bytes<OT, DV, NW>() / 16);
+    const int n16 = static_cast<int>(staged_stage_bytes<OT, DV, NW, GND>() / 16);
     for (int i = threadIdx.x; i < n16; i += 64 * NW) z[i] = float4{0.f, 0.f, 0.f, 0.f};
   }
   // Staged channels carry (f - m) instead of f, m = f at the tile centre:
