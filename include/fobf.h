@@ -194,11 +194,14 @@ fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W,
  * first paragraph; outputs as fobf_filter, up to float32 summation order)
  * with a caller-provided device workspace that holds each tile's running N
  * and D instead of the LDS.  That frees the LDS for tiles of up to 512 rows,
- * so far fewer of the vertical pass's halo rows are recomputed; the
- * two-word modes (FOBF_BF16_STAGE, FOBF_FP16X2_STAGE) use it for images
- * tall enough to give such tiles while still filling the device (e.g.
- * 2048^2 and larger at theta <= 13.5).  For every other case the workspace
- * is not used and fobf_filter_ws behaves exactly as fobf_filter.
+ * so far fewer of the vertical pass's halo rows are recomputed, and lets
+ * FOBF_FP32 stage each block's channels once per workgroup instead of once
+ * per wave (its output is then identical to fobf_filter's, bit for bit).
+ * FOBF_FP32 and the two-word modes (FOBF_BF16_STAGE, FOBF_FP16X2_STAGE) use
+ * it for images tall enough to give such tiles while still filling the
+ * device (e.g. 2048^2 and larger at theta <= 13.5).  For every other case
+ * the workspace is not used and fobf_filter_ws behaves exactly as
+ * fobf_filter.
  *
  * fobf_filter_workspace_size: *bytes = the workspace fobf_filter_ws needs
  *   for an H x W image at this theta and precision (0: none; about 8 bytes

@@ -23,6 +23,7 @@ SOURCES = [
     "fobf_lut.cpp",
     "fobf_valu.hip",
     "fobf_mfma.hip",
+    "fobf_mfma_ws.hip",
     "fobf_batch.hip",
     "fobf_tune.hip",
     "fobf_serve.cpp",

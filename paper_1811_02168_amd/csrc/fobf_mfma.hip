@@ -10,8 +10,6 @@
 
 namespace fobf {
 
-constexpr int kWsWaves = 8;   // strips per workgroup of the workspace form
-
 namespace {
 
 template <int SH>
@@ -35,14 +33,6 @@ __global__ __launch_bounds__(MTHREADS, (SH <= 20 ? 2 : 1)) void mfma_f32_kernel(
   f32_tile<SH>(im, tx, ty, nblk, tbl, Bt, At, nd);
 }
 
-// Workgroup width of the staged kernels: eight strips (wider tiles share
-// more of the horizontal halo's channel work), except for the two-word
-// bf16 staging at the largest radii (DV = 7), whose registers spill at
-// eight waves: there four are faster (4096^2, theta = 15: 2.23 vs 3.07 ms;
-// at theta = 10 and 13 eight win, 1.28 vs 1.70 and 1.81 vs 1.92 ms).
-template <typename OT, int DV>
-constexpr int staged_waves() { return (Stage<OT>::kParts == 2 && DV >= 7) ? 4 : 8; }
-
 template <typename OT, int DV>
 __global__ __launch_bounds__((64 * staged_waves<OT, DV>())) void mfma_staged_kernel(ImageParams p,
                                                                             int nblk) {
@@ -61,47 +51,7 @@ __global__ __launch_bounds__((64 * staged_waves<OT, DV>())) void mfma_staged_ker
   staged_tile<OT, DV, NW>(im, tx, ty, nblk, tbl, sbuf, nd);
 }
 
-// Tall-tile form of the staged kernel: each tile's N and D live in a global
-// workspace (2 nblk 256 floats per wave, tiles in row-major order), so the
-// LDS holds only the staging buffer and the tile can be 512 rows tall.
-template <typename OT, int DV>
-__global__ __launch_bounds__((64 * staged_waves<OT, DV>())) void mfma_staged_ws_kernel(
-    ImageParams p, int nblk, float* work) {
-  constexpr int NW = staged_waves<OT, DV>();
-  extern __shared__ float lds[];
-  const int ntx = (p.W + NW * MSTRIP - 1) / (NW * MSTRIP);
-  const int nty = (p.H + 16 * nblk - 1) / (16 * nblk);
-  int tx, ty;
-  if (!tile_of_block(blockIdx.x, gridDim.x, ntx, nty, &tx, &ty)) return;
-  float* tbl = lds;
-  typename Stage<OT>::T* sbuf = reinterpret_cast<typename Stage<OT>::T*>(lds + LDS_TABLE);
-  float* nd = work + (static_cast<size_t>(ty) * ntx + tx) * (NW * 2 * 256) * nblk;
-  FOBF_LOAD_TABLES(p, tbl);
-  const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
-  __syncthreads();
-  staged_tile<OT, DV, NW, true>(im, tx, ty, nblk, tbl, sbuf, nd);
-}
-
 // ------------------------------------------------------------------ host --
-
-template <typename KernelT>
-void allow_big_lds(KernelT kernel) {
-  hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-}
-
-// 1-D grid: tiles (nw strips wide) rounded up to a multiple of the 8 XCDs
-unsigned padded_blocks(const ImageParams& p, int nblk, int nw = MWAVES) {
-  const long ntx = (p.W + nw * MSTRIP - 1) / (nw * MSTRIP);
-  const long nty = (p.H + 16 * nblk - 1) / (16 * nblk);
-  return static_cast<unsigned>(((ntx * nty + 7) / 8) * 8);
-}
-
-fobf_status check_launch(const char* what) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(FOBF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-  return FOBF_OK;
-}
 
 template <int SH>
 fobf_status launch_f32_sh(const ImageParams& p, int nblk, void* stream) {
@@ -154,66 +104,7 @@ fobf_status launch_staged(const ImageParams& p, int DV, int nblk, void* stream) 
   }
 }
 
-template <typename OT, int DV>
-fobf_status launch_staged_ws_dv(const ImageParams& p, int nblk, float* work, void* stream) {
-  static const bool once = (allow_big_lds(mfma_staged_ws_kernel<OT, DV>), true);
-  (void)once;
-  constexpr int NW = staged_waves<OT, DV>();
-  static_assert(NW == kWsWaves, "the workspace form runs eight strips");
-  constexpr size_t lds = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV, NW, true>();
-  static_assert(lds <= 160 * 1024, "staging buffers exceed the LDS");
-  dim3 grid(padded_blocks(p, nblk, NW));
-  hipLaunchKernelGGL((mfma_staged_ws_kernel<OT, DV>), grid, dim3(64 * NW), lds,
-                     static_cast<hipStream_t>(stream), p, nblk, work);
-  return check_launch("mfma_staged_ws_kernel");
-}
-
-template <typename OT>
-fobf_status launch_staged_ws(const ImageParams& p, int DV, int nblk, float* work,
-                             void* stream) {
-  switch (DV) {
-    case 2: return launch_staged_ws_dv<OT, 2>(p, nblk, work, stream);
-    case 3: return launch_staged_ws_dv<OT, 3>(p, nblk, work, stream);
-    case 4: return launch_staged_ws_dv<OT, 4>(p, nblk, work, stream);
-    case 5: return launch_staged_ws_dv<OT, 5>(p, nblk, work, stream);
-    case 6: return launch_staged_ws_dv<OT, 6>(p, nblk, work, stream);
-    default: return fail(FOBF_EINTERNAL, "fobf_filter_ws: no workspace form for this radius");
-  }
-}
-
 }  // namespace
-
-// Tile height (16-row blocks) of the workspace form, or 0 where it is not
-// used: only the two-word modes (whose LDS otherwise caps tiles at 96 rows)
-// at radius classes DV = 2..6 (eight strips), and only when the image is
-// tall enough for tiles of at least 8 blocks while still giving about one
-// workgroup per compute unit (256 on the MI355X).  At most 32 blocks.
-int ws_nblk(const ImageParams& p, int prec) {
-  if (prec != FOBF_BF16_STAGE && prec != FOBF_FP16X2_STAGE) return 0;
-  const int DV = (MSTRIP + 2 * p.r + 15) / 16;
-  if (DV < 2 || DV > 6 || p.H < 1 || p.W < 1) return 0;
-  const long ntx = (p.W + kWsWaves * MSTRIP - 1) / (kWsWaves * MSTRIP);
-  const long rows = (p.H + 15) / 16;
-  const long nty_target = (256 + ntx - 1) / ntx;
-  const long nblk = std::min<long>(32, (rows + nty_target - 1) / nty_target);
-  return nblk >= 8 ? static_cast<int>(nblk) : 0;
-}
-
-size_t ws_bytes(const ImageParams& p, int prec) {
-  const int nblk = ws_nblk(p, prec);
-  if (nblk == 0) return 0;
-  const size_t ntx = (p.W + kWsWaves * MSTRIP - 1) / (kWsWaves * MSTRIP);
-  const size_t nty = (p.H + 16 * nblk - 1) / (16 * nblk);
-  return sizeof(float) * ntx * nty * kWsWaves * 2 * 256 * static_cast<size_t>(nblk);
-}
-
-fobf_status launch_mfma_ws(const ImageParams& p, int prec, float* work, void* stream) {
-  const int nblk = ws_nblk(p, prec);
-  const int DV = (MSTRIP + 2 * p.r + 15) / 16;
-  if (nblk == 0) return fail(FOBF_EINTERNAL, "fobf_filter_ws: no workspace form");
-  if (prec == FOBF_BF16_STAGE) return launch_staged_ws<__bf16>(p, DV, nblk, work, stream);
-  return launch_staged_ws<F16Pair>(p, DV, nblk, work, stream);
-}
 
 fobf_status launch_mfma(const ImageParams& p, int prec, int nblk, void* stream) {
   const int DV = (MSTRIP + 2 * p.r + 15) / 16;

@@ -601,6 +601,198 @@ __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shi
     }
 }
 
+// =========================================================================
+// float32, workspace form: the channels of each 16-row block staged once
+// per workgroup in LDS (float32), N and D in the global workspace
+// =========================================================================
+
+// LDS pitch (floats) of a staged float32 channel row: room for the items
+// (CWn rounded up to whole items) and the strips' reads, = 4 (mod 64) so
+// that the 16 rows x 4 column runs one ds_read covers fall in distinct banks.
+__host__ __device__ constexpr int f32s_pitch(int sh, int nw, int r, int iw) {
+  const int a = 16 * nw + 2 * r + iw, b = 16 * (nw - 1) + 4 * sh;
+  const int m = a > b ? a : b;
+  return ((m - 4 + 63) / 64) * 64 + 4;
+}
+
+// This thread's item of one block: G channels of frequency k (float32, no
+// shift) into buf[(g * 16 + row) * PC + col], col 0 = column x0 - r.
+template <int G, int IW, bool INTERIOR>
+__device__ __forceinline__ void f32s_stage(const Img& im, float kinv, int x0, int row0, int CWn,
+                                           int PC, float* buf, const float (&fvs)[IW]) {
+  const int per_row = (CWn + IW - 1) / IW;
+  const int it = threadIdx.x;
+  if (it >= 16 * per_row) return;
+  const int rr = it / per_row;
+  const int c0 = (it - rr * per_row) * IW;
+  const int row = row0 + rr;
+  const int col0 = x0 - im.r + c0;
+  const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
+  float x[G][IW];
+#pragma unroll
+  for (int j = 0; j < IW; ++j) {
+    const bool in =
+        INTERIOR || (rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W));
+    const float f = in ? fvs[j] : 0.f;
+    if (G == 1) {
+      x[0][j] = f;
+    } else {
+      float sn, cs;
+      sincos_rev(kinv * f, &sn, &cs);
+      x[0][j] = cs * f;
+      x[1][j] = sn * f;
+      x[2][j] = in ? cs : 0.f;
+      x[3][j] = in ? sn : 0.f;
+    }
+  }
+  // IW is even and c0 a multiple of it: pairs are 8-byte aligned
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int j = 0; j < IW / 2; ++j)
+      reinterpret_cast<float2*>(buf + (g * 16 + rr) * PC + c0)[j] =
+          float2{x[g][2 * j], x[g][2 * j + 1]};
+}
+
+// One channel group over the workgroup's tile: per 16-row block the
+// workgroup stages the block's channels (two buffers, one barrier per
+// block), each wave runs the horizontal pass of its strip from LDS (the
+// contraction order of f32_group: lane (li, lk), step s reads column
+// 16 wave + SH lk + s), the vertical pass from its ring and folds into the
+// block's N and D, fetched from the workspace a block ahead.
+template <int SH, int NW, int G>
+__device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0, int nblk,
+                                           const float* tbl, const float* Bt, const float* At,
+                                           float* sbuf, int PC, float* Ns, float* Ds) {
+  constexpr int DV = (SH + 3) / 4;
+  constexpr int IW = stage_item_width<DV, NW>();
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const float kinv = static_cast<float>(k) * im.inv_period;
+  const float ck = tbl[64 + k];
+  const int r = im.r;
+  const int CWn = 16 * NW + 2 * r;
+  const int x0w = x0 + wave * MSTRIP;
+  const int gxo = min(x0w + li, im.W - 1);
+  const int QB = nblk + DV - 1;
+  const bool cols_in = x0 - r >= 0 && x0 - r + IW * ((CWn + IW - 1) / IW) <= im.W;
+  auto block_interior = [&](int row0) { return cols_in && row0 >= 0 && row0 + 16 <= im.H; };
+  const size_t ld = static_cast<size_t>(im.ld_in);
+
+  f4 ring[DV][G];
+  float fvs[IW];
+  stage_fetch<IW>(im, x0, y0 - r, CWn, block_interior(y0 - r), fvs);
+  __syncthreads();   // the previous group's readers are done with both buffers
+  for (int qq = 0; qq < QB; qq += DV) {
+#pragma unroll
+    for (int u = 0; u < DV; ++u) {
+      const int q = qq + u;
+      if (q < QB) {
+        float* buf = sbuf + (q & 1) * (STAGE_CH * 16 * PC);
+        const int row0 = y0 - r + 16 * q;
+        const int pb = q - (DV - 1);
+        float fo[4], nv[4], dv[4];
+        if (pb >= 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            nv[v] = Ns[pb * 256 + 64 * v + lane];
+            if (G == 4) dv[v] = Ds[pb * 256 + 64 * v + lane];
+          }
+        }
+        if (G == 4) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
+            fo[v] = im.in[gy * ld + gxo];
+          }
+        }
+        if (block_interior(row0))
+          f32s_stage<G, IW, true>(im, kinv, x0, row0, CWn, PC, buf, fvs);
+        else
+          f32s_stage<G, IW, false>(im, kinv, x0, row0, CWn, PC, buf, fvs);
+        const int rown = y0 - r + 16 * ((q + 1 < QB) ? q + 1 : q);
+        stage_fetch<IW>(im, x0, rown, CWn, block_interior(rown), fvs);
+        __syncthreads();
+        // ---- horizontal pass of this wave's strip, from LDS ----
+        const float* arow = buf + li * PC + 16 * wave + SH * lk;
+        f4 acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < SH; ++s) {
+          const float bh = Bt[s * 64 + lane];
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+            acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[g * 16 * PC + s], bh, acc[g], 0,
+                                                          0, 0);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) ring[u][g] = acc[g];
+        // ---- vertical pass, output block pb ----
+        if (pb >= 0) {
+          f4 vacc[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) vacc[g] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int d = 0; d < DV; ++d) {
+            const int slot = (u + 1 + d) % DV;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float av = At[(d * 4 + v) * 64 + lane];
+#pragma unroll
+              for (int g = 0; g < G; ++g)
+                vacc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ring[slot][g][v], vacc[g],
+                                                               0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            if (G == 1) {
+              nv[v] = fmaf(ck, vacc[0][v], nv[v]);
+            } else {
+              float sn, cs;
+              sincos_rev(kinv * fo[v], &sn, &cs);
+              nv[v] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), nv[v]);
+              dv[v] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), dv[v]);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Ns[pb * 256 + 64 * v + lane] = nv[v];
+            if (G == 4) Ds[pb * 256 + 64 * v + lane] = dv[v];
+          }
+        }
+      }
+    }
+  }
+}
+
+// nd: this workgroup's share of the workspace, 2 nblk 256 floats per wave.
+template <int SH, int NW>
+__device__ __forceinline__ void f32s_tile(const Img& im, int tx, int ty, int nblk,
+                                          const float* tbl, const float* Bt, const float* At,
+                                          float* sbuf, int PC, float* nd) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  float* Ns = nd + wave * 2 * nblk * 256;
+  float* Ds = Ns + nblk * 256;
+  const int x0 = tx * (NW * MSTRIP);
+  const int y0 = ty * 16 * nblk;
+  // zero both staging buffers: columns past the items are read by steps
+  // whose taps are zero, so they must hold finite values
+  {
+    float4* z = reinterpret_cast<float4*>(sbuf);
+    const int n16 = 2 * STAGE_CH * 16 * PC / 4;
+    for (int i = threadIdx.x; i < n16; i += 64 * NW) z[i] = float4{0.f, 0.f, 0.f, 0.f};
+  }
+  init_nd(im, tbl, x0 + wave * MSTRIP, y0, nblk, Ns, Ds, lane);
+  f32s_group<SH, NW, 1>(im, 0, x0, y0, nblk, tbl, Bt, At, sbuf, PC, Ns, Ds);
+  for (int k = 1; k < im.K; ++k)
+    f32s_group<SH, NW, 4>(im, k, x0, y0, nblk, tbl, Bt, At, sbuf, PC, Ns, Ds);
+  store_nd(im, x0 + wave * MSTRIP, y0, nblk, Ns, Ds, lane);
+}
+
 // GND = false: N and D of the tile live in LDS (the single-image and batch
 // kernels).  GND = true: they live in a global workspace, which frees the
 // LDS for much taller tiles (fewer halo blocks per output block); the
@@ -873,6 +1065,39 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
   for (int k = 1; k < im.K; ++k)
     staged_group<OT, DV, 4, NW, GND>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
   store_nd(im, x0w, y0, nblk, Ns, Ds, lane, shift);
+}
+
+// =========================================================================
+// launch helpers shared by the single-image launch files
+// =========================================================================
+
+// Workgroup width of the staged kernels: eight strips (wider tiles share
+// more of the horizontal halo's channel work), except for the two-word
+// bf16 staging at the largest radii (DV = 7), whose registers spill at
+// eight waves: there four are faster (4096^2, theta = 15: 2.23 vs 3.07 ms;
+// at theta = 10 and 13 eight win, 1.28 vs 1.70 and 1.81 vs 1.92 ms).
+template <typename OT, int DV>
+constexpr int staged_waves() { return (Stage<OT>::kParts == 2 && DV >= 7) ? 4 : 8; }
+
+constexpr int kWsWaves = 8;   // strips per workgroup of the workspace forms
+
+template <typename KernelT>
+inline void allow_big_lds(KernelT kernel) {
+  hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+// 1-D grid: tiles (nw strips wide) rounded up to a multiple of the 8 XCDs
+inline unsigned padded_blocks(const ImageParams& p, int nblk, int nw = MWAVES) {
+  const long ntx = (p.W + nw * MSTRIP - 1) / (nw * MSTRIP);
+  const long nty = (p.H + 16 * nblk - 1) / (16 * nblk);
+  return static_cast<unsigned>(((ntx * nty + 7) / 8) * 8);
+}
+
+inline fobf_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(FOBF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return FOBF_OK;
 }
 
 }  // namespace

@@ -1,8 +1,10 @@
 """GPU parity of fobf_filter_ws, the workspace form of the filter (each
 tile's N and D in a caller-provided device workspace, tiles up to 512 rows
-tall): the two-word modes against the FP64 oracle with the same (K, T, c),
-against the LDS form, at ragged and pitched sizes of every radius class it
-covers, in a captured graph, and with a reused workspace."""
+tall; float32 also stages its channels per workgroup): float32 and the
+two-word modes against the FP64 oracle with the same (K, T, c), against the
+LDS form (bit for bit in float32: the same sums in the same order), at
+ragged and pitched sizes of every radius class it covers, in a captured
+graph, and with a reused workspace."""
 import numpy as np
 import pytest
 
@@ -12,7 +14,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp32": 0.05, "fp16x2": 0.05, "bf16": 0.5, "fp16": 0.5}
-WS_PRECS = ["bf16", "fp16x2"]
+WS_PRECS = ["fp32", "bf16", "fp16x2"]
 
 
 def fitted(sigma, K):
@@ -97,11 +99,13 @@ def test_ws_shapes_against_oracle_and_lds_form(prec, H, W, theta, K, sigma, pad)
     print("ws shape", prec, H, W, theta, K, float(err.max()), "vs lds", d)
     assert float(err.max()) <= TOL[prec]
     assert d <= 2 * TOL[prec]
+    if prec == "fp32":
+        assert d == 0.0
 
 
 def test_ws_falls_back_where_not_used():
-    """fp32, single fp16, small images and the largest radius class need no
-    workspace: fobf_filter_ws then equals fobf_filter bit for bit."""
+    """Single fp16, short or narrow images and the largest radius class need
+    no workspace: fobf_filter_ws then equals fobf_filter bit for bit."""
     import torch
     import paper_1811_02168_amd as F
     cases = [(4096, 512, 10.0, "fp32"), (2048, 2048, 10.0, "fp16"),
