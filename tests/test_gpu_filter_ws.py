@@ -182,3 +182,30 @@ def test_ws_in_a_captured_graph():
                            workspace=torch.empty_like(wss[p]))
             torch.cuda.synchronize()
             assert torch.equal(outs[p], ref), (rep, p)
+
+
+def test_ws_fp32_bitwise_random():
+    """float32 through fobf_filter_ws computes the same sums in the same
+    order as fobf_filter: seeded random large images (sizes, radius classes
+    DV = 2..6, orders, pitched buffers) give bit-identical outputs."""
+    import torch
+    import paper_1811_02168_amd as F
+    rng = np.random.default_rng(515)
+    used = 0
+    for case in range(16):
+        H = int(rng.integers(1900, 4400))
+        W = int(rng.integers(1000, 4400))
+        theta = float(rng.uniform(0.4, 13.5))
+        K = int(rng.integers(1, 17))
+        sigma = float(round(rng.uniform(15, 120)))
+        pad = int(rng.integers(0, 5))
+        f = workloads.voronoi_image(H, W, max(4, H * W // 60000), bool(case % 2), 40000 + case)
+        T, c = fitted(sigma, K)
+        got, ws_used = run_ws(f, theta, K, T, c, "fp32", pad=pad)
+        used += ws_used
+        ref = F.filter(torch.from_numpy(f.astype(np.float32)).cuda(), theta, K, T, c,
+                       prec="fp32")
+        torch.cuda.synchronize()
+        print("fp32 ws bitwise", case, H, W, round(theta, 2), K, ws_used)
+        assert np.array_equal(got, ref.cpu().numpy().astype(np.float64)), (case, H, W, theta)
+    assert used >= 12
