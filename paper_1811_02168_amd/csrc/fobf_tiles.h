@@ -607,8 +607,9 @@ __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shi
 // =========================================================================
 
 // LDS pitch (floats) of a staged float32 channel row: room for the items
-// (CWn rounded up to whole items) and the strips' reads, = 4 (mod 64) so
-// that the 16 rows x 4 column runs one ds_read covers fall in distinct banks.
+// (CWn rounded up to whole items) and the strips' reads, = 4 (mod 64), which
+// spreads the 16 rows x 4 column runs of one read over the banks (a pitch
+// = 2 (mod 32) measured within 1.5%).
 __host__ __device__ constexpr int f32s_pitch(int sh, int nw, int r, int iw) {
   const int a = 16 * nw + 2 * r + iw, b = 16 * (nw - 1) + 4 * sh;
   const int m = a > b ? a : b;
