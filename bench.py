@@ -46,7 +46,7 @@ def parse():
                     help="timed requests of the warm-cache serving leg (after "
                     "a tenth as many warm-up requests); the cold-cache leg "
                     "times a quarter as many")
-    ap.add_argument("--modes", default="fp32,fp32_ws,fp16,bf16,fp16x2,bf16_ws,fp16x2_ws",
+    ap.add_argument("--modes", default="fp32,fp32_ws,fp16,fp16_ws,bf16,fp16x2,bf16_ws,fp16x2_ws",
                     help="precisions; a _ws suffix calls fobf_filter_ws with a workspace")
     ap.add_argument("--profile-run", action="store_true",
                     help="for rocprofv3 counter passes: one 256 MiB device "
@@ -69,13 +69,14 @@ KERNEL_LABELS = {
     "mfma_staged_f16_c3": "fp16-staged (16x16x32 f16, fp32 accumulation)",
     "mfma_staged_bf16_c3": "bf16 hi+lo staged (16x16x32 bf16, fp32 accumulation)",
     "mfma_staged_f16x2_c3": "fp16 hi+lo staged (16x16x32 f16, fp32 accumulation)",
+    "mfma_staged_ws_f16_c3": "fp16-staged, workspace form (512-row tiles)",
     "mfma_staged_ws_bf16_c3": "bf16 hi+lo staged, workspace form (512-row tiles)",
     "mfma_staged_ws_f16x2_c3": "fp16 hi+lo staged, workspace form (512-row tiles)",
 }
 
 
 MODE_TRAFFIC = {"fp32": "mfma_f32_kernel_c3", "fp32_ws": "mfma_f32_ws_kernel_c3",
-                "fp16": "mfma_staged_f16_c3", "bf16": "mfma_staged_bf16_c3",
+                "fp16": "mfma_staged_f16_c3", "fp16_ws": "mfma_staged_ws_f16_c3", "bf16": "mfma_staged_bf16_c3",
                 "fp16x2": "mfma_staged_f16x2_c3", "bf16_ws": "mfma_staged_ws_bf16_c3",
                 "fp16x2_ws": "mfma_staged_ws_f16x2_c3"}
 
@@ -173,6 +174,8 @@ TRAFFIC_KERNELS = {            # key -> substrings naming the kernel
     "mfma_staged_bf16_c3": ("mfma_staged_kernel<__bf16, 5>", "mfma_staged_kernelIDF16bLi5E"),
     "mfma_staged_f16x2_c3": ("mfma_staged_kernel<fobf::(anonymous namespace)::F16Pair, 5>",
                              "mfma_staged_kernelINS0_7F16PairELi5E"),
+    "mfma_staged_ws_f16_c3": ("mfma_staged_ws_kernel<_Float16, 5>",
+                              "mfma_staged_ws_kernelIDF16_Li5E"),
     "mfma_staged_ws_bf16_c3": ("mfma_staged_ws_kernel<__bf16, 5>",
                                "mfma_staged_ws_kernelIDF16bLi5E"),
     "mfma_staged_ws_f16x2_c3": ("mfma_staged_ws_kernel<fobf::(anonymous namespace)::F16Pair, 5>",

@@ -199,9 +199,9 @@ fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W,
  * per wave (its output is then identical to fobf_filter's, bit for bit).
  * FOBF_FP32 and the two-word modes (FOBF_BF16_STAGE, FOBF_FP16X2_STAGE) use
  * it for images tall enough to give such tiles while still filling the
- * device (e.g. 2048^2 and larger at theta <= 13.5).  For every other case
- * the workspace is not used and fobf_filter_ws behaves exactly as
- * fobf_filter.
+ * device (e.g. 2048^2 and larger at theta <= 13.5), FOBF_FP16_STAGE for
+ * those at 8.7 < theta <= 13.5.  For every other case the workspace is not
+ * used and fobf_filter_ws behaves exactly as fobf_filter.
  *
  * fobf_filter_workspace_size: *bytes = the workspace fobf_filter_ws needs
  *   for an H x W image at this theta and precision (0: none; about 8 bytes

@@ -116,14 +116,15 @@ fobf_status launch_staged_ws(const ImageParams& p, int DV, int nblk, float* work
 // Tile height (16-row blocks) of the workspace forms, or 0 where they are
 // not used: float32 and the two-word modes (whose LDS otherwise caps the
 // tiles at 128 and 96 rows) at radius classes DV = 2..6 (eight strips),
-// and only when the image is tall enough for tiles of at least 8 blocks
-// while still giving about one workgroup per compute unit (256 on the
-// MI355X).  At most 32 blocks.  (Single-word fp16 gains too little: it
-// keeps the LDS form.)
+// single-word fp16 at DV = 5..6 only (measured at 4096^2: theta 10 and 12
+// 9% and 17% faster, theta 8 equal, theta 5 5% slower), and only when the
+// image is tall enough for tiles of at least 8 blocks while still giving
+// about one workgroup per compute unit (256 on the MI355X).  At most 32
+// blocks.
 int ws_nblk(const ImageParams& p, int prec) {
-  if (prec != FOBF_FP32 && prec != FOBF_BF16_STAGE && prec != FOBF_FP16X2_STAGE) return 0;
+  if (prec < FOBF_FP32 || prec > FOBF_FP16X2_STAGE) return 0;
   const int DV = (MSTRIP + 2 * p.r + 15) / 16;
-  if (DV < 2 || DV > 6 || p.H < 1 || p.W < 1) return 0;
+  if (DV < (prec == FOBF_FP16_STAGE ? 5 : 2) || DV > 6 || p.H < 1 || p.W < 1) return 0;
   const long ntx = (p.W + kWsWaves * MSTRIP - 1) / (kWsWaves * MSTRIP);
   const long rows = (p.H + 15) / 16;
   const long nty_target = (256 + ntx - 1) / ntx;
@@ -151,6 +152,7 @@ fobf_status launch_mfma_ws(const ImageParams& p, int prec, float* work, void* st
       return fail(FOBF_EINTERNAL, "fobf_filter_ws: no workspace form for this radius");
     return table[SH - kWsMinSH](p, nblk, work, stream);
   }
+  if (prec == FOBF_FP16_STAGE) return launch_staged_ws<_Float16>(p, DV, nblk, work, stream);
   if (prec == FOBF_BF16_STAGE) return launch_staged_ws<__bf16>(p, DV, nblk, work, stream);
   return launch_staged_ws<F16Pair>(p, DV, nblk, work, stream);
 }

@@ -122,14 +122,15 @@ def test_fit_invalid_arguments():
 
 def test_filter_workspace_without_device():
     """fobf_filter_workspace_size is host arithmetic: zero where the
-    workspace form is not used (single fp16, small images, the largest
-    radius class), 8 bytes per pixel of whole tiles otherwise; and
+    workspace form is not used (single fp16 below DV = 5, small images, the
+    largest radius class), 8 bytes per pixel of whole tiles otherwise; and
     fobf_filter_ws rejects bad arguments and a missing, short, misaligned or
     overlapping workspace on the host, before any HIP call."""
     import ctypes as C
     import paper_1811_02168_amd as F
     size = F.filter_workspace_size
-    assert size(4096, 4096, 10.0, "fp16") == 0
+    assert size(4096, 4096, 8.0, "fp16") == 0             # single fp16: DV >= 5 only
+    assert size(4096, 4096, 10.0, "fp16") == 8 * 4096 * 4096
     for prec in ("fp32", "bf16", "fp16x2"):
         assert size(1024, 1024, 10.0, prec) == 0            # tiles would be short
         assert size(4096, 4096, 15.0, prec) == 0            # radius class DV = 7
