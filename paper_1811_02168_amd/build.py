@@ -1,6 +1,6 @@
 """Build libfobf.so (HIP for gfx950 + host C++) in-tree with hipcc.
 
-Usage: python -m paper_1811_02168_amd.build   (or call build()).
+Usage: python paper_1811_02168_amd/build.py   (or call build()).
 Every call recompiles all sources.
 """
 from __future__ import annotations

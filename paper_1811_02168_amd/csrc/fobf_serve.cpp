@@ -3,7 +3,7 @@
 // submit() may be called from any thread at any time; it validates the
 // request, stamps it and queues it.  One scheduler thread admits queued
 // requests in arrival order while the number in flight and their device
-// bytes (input + output image) fit the configured limits, merges up to
+// bytes (below) fit the configured limits, merges up to
 // max_batch admitted requests into one batch, and issues the batch on the
 // next of a few HIP streams ("lanes"): per request a stream-ordered device
 // allocation and the host-to-device copy, then ONE persistent batched
@@ -20,7 +20,16 @@
 // coefficients are ready: the scheduler admits, in arrival order, the
 // queued requests whose fit has finished.  Each distinct fit is uploaded
 // once into a device-resident table that the batched kernel reads them
-// from.
+// from.  Ordering rule: the upload of a row is enqueued on the lane of the
+// first batch that uses it, followed by an event; every later batch that
+// reads the row, on whatever lane, waits for that event on its own lane
+// before its kernel (until the event has been seen complete), so no
+// kernel can read a row before its bytes have landed.
+//
+// Device memory: request images, and each batch's job table, come from a
+// memory pool private to the server whose release threshold is the HBM
+// budget (the process's default pool is left untouched); each request is
+// charged its two images plus one batch-workspace share against the budget.
 //
 // Host image buffers should be pinned (hipHostMalloc, or torch's
 // pin_memory) for the copies to be asynchronous; pageable buffers work but
@@ -111,10 +120,13 @@ struct fobf_server {
     int T;
     double c[FOBF_KMAX];
     const float* row;
+    hipEvent_t uploaded;   // recorded after the row's upload (or null)
+    bool landed;           // the event has been seen complete
   };
   std::map<CoefKey, Coef> coef;
   float* d_coef = nullptr;
   int coef_used = 0;
+  hipMemPool_t pool = nullptr;   // private pool for request buffers
   fobf_serve_stats stats{};
 };
 
@@ -168,6 +180,21 @@ void finish_now(fobf_server* s, const std::vector<Req*>& qs, fobf_status st) {
   s->cv_work.notify_all();
 }
 
+// Stream-ordered device allocation from the server's private pool (or the
+// device's default pool where a private one could not be created).
+hipError_t device_alloc(fobf_server* s, void** p, size_t bytes, hipStream_t st) {
+  *p = nullptr;
+  if (s->pool) return hipMallocFromPoolAsync(p, bytes, s->pool, st);
+  return hipMallocAsync(p, bytes, st);
+}
+
+// Device bytes a request is charged against the budget: its input and
+// output images plus one batch-workspace share (job-table entry and the
+// launch counters), so that every batch's workspace is covered too.
+size_t request_bytes(int H, int W) {
+  return 2 * sizeof(float) * static_cast<size_t>(H) * W + batch_workspace_bytes(1);
+}
+
 // Coefficients of an admitted request (its fit has finished): the first
 // use of a fit uploads its float32 row into the device table.  Scheduler
 // thread only.
@@ -182,12 +209,35 @@ fobf_status coefficients(fobf_server* s, Req* q, hipStream_t st) {
     float row[FOBF_KMAX];
     for (int k = 0; k < FOBF_KMAX; ++k) row[k] = k < q->r.K ? static_cast<float>(e.c[k]) : 0.f;
     float* dst = s->d_coef + static_cast<size_t>(s->coef_used) * FOBF_KMAX;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+      return fail(FOBF_EHIP, "fobf_serve: event creation failed");
     fobf_status up = upload_async(dst, row, sizeof(row), st);
-    if (up != FOBF_OK) return up;
+    if (up == FOBF_OK && hipEventRecord(ev, st) != hipSuccess)
+      up = fail(FOBF_EHIP, "fobf_serve: event record failed");
+    if (up != FOBF_OK) {
+      hipEventDestroy(ev);
+      return up;
+    }
     s->coef_used += 1;
     e.row = dst;
+    e.uploaded = ev;
+    e.landed = false;
     std::lock_guard<std::mutex> lk(s->mu);
-    s->coef.at(q->key).row = dst;
+    fobf_server::Coef& m = s->coef.at(q->key);
+    m.row = dst;
+    m.uploaded = ev;
+    m.landed = false;
+  } else if (e.row && e.uploaded && !e.landed) {
+    // the row was uploaded by an earlier batch, possibly on another lane:
+    // order this lane after the upload unless it is known to have landed
+    const hipError_t qe = hipEventQuery(e.uploaded);
+    if (qe == hipSuccess) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->coef.at(q->key).landed = true;
+    } else if (hipStreamWaitEvent(st, e.uploaded, 0) != hipSuccess) {
+      return fail(FOBF_EHIP, "fobf_serve: stream wait on the coefficient upload failed");
+    }
   }
   q->T = e.T;
   std::memcpy(q->c, e.c, sizeof(q->c));
@@ -255,8 +305,8 @@ void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
       continue;
     }
     const size_t img = sizeof(float) * static_cast<size_t>(q->r.H) * q->r.W;
-    if (hipMallocAsync(reinterpret_cast<void**>(&q->d_in), img, st) != hipSuccess ||
-        hipMallocAsync(reinterpret_cast<void**>(&q->d_out), img, st) != hipSuccess) {
+    if (device_alloc(s, reinterpret_cast<void**>(&q->d_in), img, st) != hipSuccess ||
+        device_alloc(s, reinterpret_cast<void**>(&q->d_out), img, st) != hipSuccess) {
       if (q->d_in) hipFreeAsync(q->d_in, st);
       q->d_in = q->d_out = nullptr;
       q->res.status = FOBF_ENOMEM;
@@ -295,7 +345,7 @@ void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
   void* ws = nullptr;
   const size_t wsb = batch_workspace_bytes(static_cast<int>(jobs.size()));
   fobf_status st_b = FOBF_OK;
-  if (hipMallocAsync(&ws, wsb, st) != hipSuccess) {
+  if (device_alloc(s, &ws, wsb, st) != hipSuccess) {
     st_b = fail(FOBF_ENOMEM, "fobf_serve: workspace allocation failed");
   } else {
     st_b = filter_batch_impl(jobs.data(), static_cast<int>(jobs.size()), ws, wsb, st, cdev.data());
@@ -418,11 +468,21 @@ extern "C" fobf_status fobf_serve_create(const fobf_serve_cfg* cfg, fobf_server*
     delete s;
     return fail(FOBF_ENOMEM, "fobf_serve_create: coefficient table allocation failed");
   }
-  // keep freed stream-ordered memory in the pool (resident) between batches
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  // a private pool for request buffers: freed stream-ordered memory stays
+  // resident between batches up to the budget, and beyond it is released;
+  // the process's default pool is not touched
+  {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = s->device;
+    if (hipMemPoolCreate(&s->pool, &props) == hipSuccess) {
+      uint64_t thr = cfg->hbm_budget_bytes;
+      hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &thr);
+    } else {
+      (void)hipGetLastError();
+      s->pool = nullptr;
+    }
   }
   s->worker = std::thread(worker_main, s);
   for (auto& f : s->fitters) f = std::thread(fitter_main, s);
@@ -445,7 +505,7 @@ extern "C" fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad K");
   if (req->prec < FOBF_FP32 || req->prec > FOBF_FP16X2_STAGE)
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad precision");
-  const size_t bytes = 2 * sizeof(float) * static_cast<size_t>(req->H) * req->W;
+  const size_t bytes = request_bytes(req->H, req->W);
   if (bytes > s->cfg.hbm_budget_bytes)
     return fail(FOBF_ENOMEM, "fobf_serve_submit: request larger than the HBM budget");
   Req* q = new Req();
@@ -528,6 +588,9 @@ extern "C" fobf_status fobf_serve_destroy(fobf_server* s) {
     hipStreamDestroy(s->lanes[i]);
   }
   hipFree(s->d_coef);
+  for (auto& kv : s->coef)
+    if (kv.second.uploaded) hipEventDestroy(kv.second.uploaded);
+  if (s->pool) hipMemPoolDestroy(s->pool);
   for (auto& kv : s->reqs) delete kv.second;
   delete s;
   return FOBF_OK;

@@ -89,7 +89,7 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with "
-            "`python -m paper_1811_02168_amd.build` (no CPU fallback exists)")
+            "`python paper_1811_02168_amd/build.py` (no CPU fallback exists)")
     lib = C.CDLL(LIB_PATH)
     lib.fobf_fit.argtypes = [C.c_int, C.c_double, C.c_int, C.c_double, C.c_int,
                              C.POINTER(_Coef)]

@@ -357,6 +357,47 @@ def test_serve_many_cold_keys():
         assert float(np.max(np.abs(o - ref))) <= 1e-3
 
 
+def test_serve_coefficient_row_ordering_across_lanes():
+    """Regression test of the coefficient-row ordering rule: a key's device
+    row is uploaded on the lane of its first batch, queued behind that
+    lane's earlier work (two 4096^2 requests keep two lanes busy), while
+    later batches with the same new key run on an idle lane.  Each of those
+    must wait for the upload: every output equals the single-image batch
+    launch of its request bit for bit (a read of the row before it lands
+    gives garbage or NaN)."""
+    import torch
+    import paper_1811_02168_amd as F
+    def pinned(a):
+        # pinned host buffers: the copies stay asynchronous, so the
+        # scheduler never waits for a busy lane before issuing the next batch
+        t = torch.empty(a.shape, dtype=torch.float32, pin_memory=True).numpy()
+        t[:] = a
+        return t
+
+    big = pinned(workloads.C3.image())
+    small = [pinned(workloads.C2.image()[64 * i:64 * i + 200, 32 * i:32 * i + 230])
+             for i in range(8)]
+    key_a, key_b = (43.0, 5), (57.0, 7)          # keys no other test uses
+    F.fit_cache_clear()
+    reqs = [(big, 4.0, key_a), (big, 4.0, key_a), (small[0], 3.0, key_a)]
+    reqs += [(small[i], 2.5 + 0.25 * i, key_b) for i in range(1, 8)]
+    outs = [pinned(np.full(f.shape, np.nan)) for f, _, _ in reqs]
+    with F.Server(hbm_budget_bytes=8 << 30, max_inflight=16, max_batch=1) as srv:
+        ts = [srv.submit(f, o, theta, s, K) for (f, theta, (s, K)), o in zip(reqs, outs)]
+        res = [srv.poll(t, wait=True) for t in ts]
+    for i, ((f, theta, (s, K)), o, (st, r)) in enumerate(zip(reqs, outs, res)):
+        assert st == 0, (i, F.last_error())
+        coef = F.fit(255, s, K, eps=0.1)
+        assert r.T == coef.T
+        img = dev_img(f)
+        ref = torch.full_like(img, -1.0)
+        F.filter_batch([F.make_job(img, ref, theta, K, coef.T, coef.c)])
+        torch.cuda.synchronize()
+        ref = ref.cpu().numpy()
+        assert np.all(np.isfinite(o)), i
+        assert np.array_equal(o, ref), (i, float(np.nanmax(np.abs(o - ref))))
+
+
 def test_instruction_rate_probes_are_plausible():
     """fobf_peak: every measured rate is positive and within 10% above the
     published MI355X figure for its class (the matrix peaks are dense)."""

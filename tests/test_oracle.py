@@ -303,3 +303,42 @@ def test_psnr_above_40db_at_eps_0p1():
         out = O.fourier_direct(f, theta, a["K"], a["T"], a["c"])
         bf = O.brute_bf(f, theta, O.gaussian_range(sigma))
         assert O.psnr(bf, out) > 40.0
+
+
+def test_row_bands_equal_the_whole_image_oracle():
+    """The row-band driver (oracle/bands.py) only splits and stacks: on an
+    image with ragged bands, bands thinner than the radius and an image
+    shorter than the radius, its (out, N, D, W) equal the single-process
+    oracle bit for bit."""
+    from oracle.bands import BandPool
+    rng = np.random.default_rng(3)
+    cases = [(workloads.voronoi_image(150, 90, 9, True, 21), 3.0, 5, 7),
+             (rng.uniform(0, 255, size=(7, 40)), 4.0, 3, 3),
+             (workloads.voronoi_image(61, 33, 4, False, 22), 2.5, 13, 4)]
+    with BandPool(workers=3) as pool:
+        for f, theta, nbands, K in cases:
+            r = O.fit(255, 30.0, K, Tmax=400)
+            out, num, den = O.fourier_direct(f, theta, K, r["T"], r["c"], return_nd=True)
+            b = pool.fourier_direct(f, theta, K, r["T"], r["c"], nbands=nbands)
+            assert np.array_equal(b[0], out) and np.array_equal(b[1], num)
+            assert np.array_equal(b[2], den)
+            assert np.array_equal(b[3], O.blur_weight(*f.shape, theta))
+
+
+def test_full_image_stats_on_planted_errors():
+    """full_image_stats: masked count from the oracle's D/W, error maxima
+    split by the mask, PSNR over all and over unmasked pixels."""
+    from oracle.bands import full_image_stats
+    ref = np.full((10, 10), 100.0)
+    Wi = np.full((10, 10), 2.0)
+    den = np.full((10, 10), 1.0)
+    den[0, 0] = 0.01          # D/W = 0.005: masked
+    got = ref.copy()
+    got[0, 0] += 40.0         # masked pixel, large error
+    got[5, 5] += 0.25
+    s = full_image_stats(got, ref, den, Wi)
+    assert s["masked"] == 1 and s["pixels"] == 100
+    assert s["maxabs_unmasked"] == 0.25 and s["maxabs_masked"] == 40.0
+    assert s["maxabs_all"] == 40.0
+    assert s["psnr_unmasked_db"] == pytest.approx(10 * math.log10(255.0 ** 2 / (0.0625 / 99)))
+    assert s["psnr_all_db"] == pytest.approx(10 * math.log10(255.0 ** 2 / ((1600 + 0.0625) / 100)))
