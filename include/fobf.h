@@ -37,7 +37,8 @@ extern "C" {
 
 typedef enum {
   FOBF_OK = 0,
-  FOBF_WARN_TOL = 1,   /* fit done, but its kernel error E exceeds eps      */
+  FOBF_WARN_TOL = 1,   /* fit done, but its kernel error E exceeds eps; or a
+                          filter ran FOBF_FP16_STAGE as FOBF_FP16X2_STAGE  */
   FOBF_EBUSY = 2,      /* serving: not finished yet / no capacity, retry    */
   FOBF_EINVAL = -1,    /* invalid argument                                  */
   FOBF_ENOMEM = -2,    /* allocation failed or request exceeds the budget   */
@@ -49,9 +50,11 @@ typedef enum {
 typedef enum {
   FOBF_FP32 = 0,        /* channels and intermediates stored in float32     */
   FOBF_FP16_STAGE = 1,  /* channels/intermediates staged in fp16, fp32 acc.
-                           Error ~ 2^-9 sum|c_k| (local contrast) / (D/W):
-                           where a crude series (small K) leaves D/W small,
-                           use a two-word mode                              */
+                           Error ~ 2^-9 sum|c_k| (local contrast) / (D/W).
+                           Used only for series without negative lobes
+                           (fobf_effective_prec); a crude series, whose
+                           lobes leave D/W small, runs as FOBF_FP16X2_STAGE
+                           and the call returns FOBF_WARN_TOL               */
   FOBF_BF16_STAGE = 2,  /* staged as two bf16 words (hi + lo), fp32 acc      */
   FOBF_FP16X2_STAGE = 3 /* staged as two fp16 words (hi + lo), fp32 acc:
                            float32-class accuracy on the fp16 matrix cores  */
@@ -182,12 +185,30 @@ fobf_status fobf_fit_samples(int R, const double* b, int K, double eps,
  * H, W >= 1, ld >= W.  H == 0 or W == 0 is a no-op returning FOBF_OK.
  * Enqueues kernels only (no allocation, copy or memset), so the call can
  * be captured in a HIP graph; launch errors are returned, device faults
- * surface at the caller's next synchronisation.
+ * surface at the caller's next synchronisation.  Returns FOBF_WARN_TOL
+ * (output valid) when FOBF_FP16_STAGE ran as FOBF_FP16X2_STAGE
+ * (fobf_effective_prec).
  */
 fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W,
                         int ld_in, int ld_out, double theta, int K, int T,
                         const double* c, int prec, int algo,
                         void* hip_stream);
+
+/*
+ * fobf_effective_prec -- the precision fobf_filter, fobf_filter_ws,
+ * fobf_filter_batch and the server run for the requested `prec` and the
+ * cosine series (K, T, c) of eq. (3).  Every precision runs as requested
+ * except FOBF_FP16_STAGE for a series whose lowest value over one period
+ * (2T+1) is below -1% of its peak: D/W, the window average of the series
+ * over a pixel's neighbours, then comes close to zero where the negative
+ * lobes meet the image's contrast, the output N/D magnifies fp16's
+ * rounding past half an intensity level, and the call runs two-word fp16
+ * staging (FOBF_FP16X2_STAGE) instead.  The filter calls return
+ * FOBF_WARN_TOL (output valid, message in fobf_last_error) when they do
+ * so.  Host-only; returns -1 for an invalid prec, K (1..FOBF_KMAX), T (>= 1)
+ * or a NULL c.
+ */
+int fobf_effective_prec(int prec, int K, int T, const double* c);
 
 /*
  * fobf_filter_workspace_size / fobf_filter_ws -- the same filter (Sec. II,
@@ -205,8 +226,9 @@ fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W,
  *
  * fobf_filter_workspace_size: *bytes = the workspace fobf_filter_ws needs
  *   for an H x W image at this theta and precision (0: none; about 8 bytes
- *   per pixel otherwise).  Host-only, no device work.  Validates H, W >= 0,
- *   theta, prec and bytes != NULL (FOBF_EINVAL).
+ *   per pixel otherwise; for FOBF_FP16_STAGE, what FOBF_FP16X2_STAGE needs,
+ *   since such a call may run in that mode).  Host-only, no device work.
+ *   Validates H, W >= 0, theta, prec and bytes != NULL (FOBF_EINVAL).
  * fobf_filter_ws: arguments as fobf_filter, plus d_work (device memory, 4-
  *   byte aligned, overlapping neither image) of work_bytes >=
  *   fobf_filter_workspace_size; FOBF_EINVAL when it is needed and missing,
@@ -246,7 +268,9 @@ typedef struct {
  * d_work    device workspace of at least fobf_batch_workspace_size(n)
  *           bytes, 256-byte aligned, caller-owned, not used by another
  *           call until this call's work on the stream has finished.
- * Same rules per job as fobf_filter (algorithm: matrix cores).  Jobs with
+ * Same rules per job as fobf_filter (algorithm: matrix cores; a job's
+ * FOBF_FP16_STAGE may run as FOBF_FP16X2_STAGE, fobf_effective_prec, and
+ * the call then returns FOBF_WARN_TOL naming the last such job).  Jobs with
  * H == 0 or W == 0 are skipped; n == 0 is a no-op.  Unlike fobf_filter
  * (kernels only, capturable in a HIP graph), a batch call copies its job
  * table from library-owned pinned memory, so it is not meant for graph
@@ -311,6 +335,8 @@ typedef struct {
   fobf_status status;       /* FOBF_EBUSY while pending                    */
   double t_submit, t_admit, t_start, t_done;   /* seconds, monotonic clock */
   int T;                    /* fitted period used                          */
+  int prec;                 /* precision the request ran in (see           */
+                            /* fobf_effective_prec)                        */
 } fobf_result;
 
 fobf_status fobf_serve_create(const fobf_serve_cfg* cfg, fobf_server** out);

@@ -1,4 +1,5 @@
 // C ABI entry points: validation, parameter packing and dispatch.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -53,6 +54,54 @@ void make_params(ImageParams& p, const float* in, float* out, int H, int W,
   }
 }
 
+// Single-word fp16 staging rounds every staged channel value, tap and
+// horizontal result to 11 significant bits.  The output is N/D, and D/W is
+// the window average of the series phi_hat(f_j - f_i) over the pixel's
+// neighbours (Sec. II, first paragraph), so that rounding reaches the
+// output divided by D/W.  A series with negative lobes (a crude fit: small
+// K for its sigma) drives D/W towards zero wherever the lobes meet the
+// image's contrast, and there fp16 misses half an intensity level by far
+// (4 levels at K = 2, sigma = 34).  The check: the lowest value of the
+// series over one period, relative to its peak.  phi_hat is even and has
+// period 2T+1, so t in [0, T + 1/2] covers it; 16 K samples put 32 on
+// each period of the highest term, which places the sampled minimum within
+// 0.5% of that term's amplitude of the true one.
+bool fp16_stage_safe(int K, int T, const double* c) {
+  const int n = 16 * K;
+  const double half = T + 0.5;
+  const double nu = 2.0 * M_PI / (2.0 * T + 1.0);
+  double lo = 0.0, hi = 0.0;
+  for (int i = 0; i <= n; ++i) {
+    const double x = nu * half * i / n;
+    // cos(k x) by the three-term recurrence cos((k+1)x) = 2 cos x cos kx - cos((k-1)x)
+    const double c1 = std::cos(x);
+    double cm = 1.0, ck = c1, v = c[0];
+    for (int k = 1; k < K; ++k) {
+      v += c[k] * ck;
+      const double nx = 2.0 * c1 * ck - cm;
+      cm = ck;
+      ck = nx;
+    }
+    if (i == 0) lo = hi = v;
+    lo = std::min(lo, v);
+    hi = std::max(hi, v);
+  }
+  return hi > 0.0 && lo >= -kFp16LobeLimit * hi;
+}
+
+int effective_prec(int prec, int K, int T, const double* c) {
+  if (prec == FOBF_FP16_STAGE && !fp16_stage_safe(K, T, c)) return FOBF_FP16X2_STAGE;
+  return prec;
+}
+
+fobf_status prec_status(int requested, int used, const char* who) {
+  if (requested == used) return FOBF_OK;
+  return fail(FOBF_WARN_TOL, std::string(who) +
+                                 ": the cosine series dips below -1% of its peak, where "
+                                 "single-word fp16 staging loses half an intensity level; "
+                                 "ran with two-word fp16 staging (FOBF_FP16X2_STAGE)");
+}
+
 fobf_status validate_filter(const float* in, const float* out, int H, int W,
                             int ld_in, int ld_out, double theta, int K, int T,
                             const double* c, int prec, int algo) {
@@ -97,13 +146,15 @@ extern "C" fobf_status fobf_filter(const float* d_in, float* d_out, int H, int W
                                    T, c, prec, algo);
   if (st != FOBF_OK) return st;
   if (H == 0 || W == 0) return FOBF_OK;
+  const int eff = effective_prec(prec, K, T, c);
   ImageParams p;
   make_params(p, d_in, d_out, H, W, ld_in, ld_out, theta, K, T, c);
   const int dv = (16 + 2 * p.r + 15) / 16;
-  const TuneChoice tc = tuned(prec, dv);
-  if (algo == FOBF_ALGO_AUTO) algo = (prec == FOBF_FP32) ? tc.algo : FOBF_ALGO_MFMA;
+  const TuneChoice tc = tuned(eff, dv);
+  if (algo == FOBF_ALGO_AUTO) algo = (eff == FOBF_FP32) ? tc.algo : FOBF_ALGO_MFMA;
   if (algo == FOBF_ALGO_VALU) return launch_valu(p, hip_stream);
-  return launch_mfma(p, prec, tc.nblk, hip_stream);
+  st = launch_mfma(p, eff, tc.nblk, hip_stream);
+  return st == FOBF_OK ? prec_status(prec, eff, "fobf_filter") : st;
 }
 
 extern "C" fobf_status fobf_filter_workspace_size(int H, int W, double theta, int prec,
@@ -120,7 +171,9 @@ extern "C" fobf_status fobf_filter_workspace_size(int H, int W, double theta, in
   p.H = H;
   p.W = W;
   p.r = r;
-  *bytes = ws_bytes(p, prec);
+  // FOBF_FP16_STAGE may run as FOBF_FP16X2_STAGE (effective_prec), whose
+  // workspace form covers more radius classes: size for that
+  *bytes = ws_bytes(p, prec == FOBF_FP16_STAGE ? FOBF_FP16X2_STAGE : prec);
   return FOBF_OK;
 }
 
@@ -133,7 +186,8 @@ extern "C" fobf_status fobf_filter_ws(const float* d_in, float* d_out, int H, in
   if (H == 0 || W == 0) return FOBF_OK;
   ImageParams p;
   make_params(p, d_in, d_out, H, W, ld_in, ld_out, theta, K, T, c);
-  const size_t need = ws_bytes(p, prec);
+  const int eff = effective_prec(prec, K, T, c);
+  const size_t need = ws_bytes(p, eff);
   if (need == 0 || algo == FOBF_ALGO_VALU)
     return fobf_filter(d_in, d_out, H, W, ld_in, ld_out, theta, K, T, c, prec, algo,
                        hip_stream);
@@ -150,7 +204,14 @@ extern "C" fobf_status fobf_filter_ws(const float* d_in, float* d_out, int H, in
   const char* b1 = b0 + sizeof(float) * ((static_cast<size_t>(H) - 1) * ld_out + W);
   if ((w0 < a1 && a0 < w1) || (w0 < b1 && b0 < w1))
     return fail(FOBF_EINVAL, "fobf_filter_ws: workspace overlaps an image");
-  return launch_mfma_ws(p, prec, static_cast<float*>(d_work), hip_stream);
+  st = launch_mfma_ws(p, eff, static_cast<float*>(d_work), hip_stream);
+  return st == FOBF_OK ? prec_status(prec, eff, "fobf_filter_ws") : st;
+}
+
+extern "C" int fobf_effective_prec(int prec, int K, int T, const double* c) {
+  if (prec < FOBF_FP32 || prec > FOBF_FP16X2_STAGE || K < 1 || K > FOBF_KMAX || T < 1 || !c)
+    return -1;
+  return effective_prec(prec, K, T, c);
 }
 
 extern "C" const char* fobf_last_error(void) { return fobf::error_cstr(); }

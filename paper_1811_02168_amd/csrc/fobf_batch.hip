@@ -254,6 +254,7 @@ fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t 
   };
   std::vector<Entry> es;
   es.reserve(n);
+  int rerouted = -1;   // last job whose fp16 staging runs as two-word fp16
   for (int i = 0; i < n; ++i) {
     const fobf_job& j = jobs[i];
     fobf_status st = validate_filter(j.d_in, j.d_out, j.H, j.W, j.ld_in, j.ld_out, j.theta, j.K,
@@ -263,19 +264,21 @@ fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t 
       return st;
     }
     if (j.H == 0 || j.W == 0) continue;
+    const int prec = effective_prec(j.prec, j.K, j.T, j.c);
+    if (prec != j.prec) rerouted = i;
     Entry e;
     std::memset(&e.b, 0, sizeof(e.b));
     make_params(e.b.p, j.d_in, j.d_out, j.H, j.W, j.ld_in, j.ld_out, j.theta, j.K, j.T, j.c);
     e.b.p.c_dev = c_dev ? c_dev[i] : nullptr;
     const int r = e.b.p.r;
     e.b.dv = (16 + 2 * r + 15) / 16;
-    e.b.nblk = std::min(batch_tile_blocks(j.prec, e.b.dv, j.H),
-                        class_nblk_cap(j.prec, radius_class(e.b.dv)));
+    e.b.nblk = std::min(batch_tile_blocks(prec, e.b.dv, j.H),
+                        class_nblk_cap(prec, radius_class(e.b.dv)));
     e.b.ntx = (j.W + MWAVES * MSTRIP - 1) / (MWAVES * MSTRIP);
     e.b.nty = (j.H + 16 * e.b.nblk - 1) / (16 * e.b.nblk);
     // cost of one tile ~ channels x (halo'd rows) x band
     e.cost = static_cast<double>(4 * j.K - 3) * (e.b.nblk + e.b.dv - 1) * (2 * r + 1);
-    e.cls = j.prec * kRadiusClasses + radius_class(e.b.dv);
+    e.cls = prec * kRadiusClasses + radius_class(e.b.dv);
     es.push_back(e);
   }
   // per class: largest tiles first (their tail is the hardest to hide)
@@ -314,6 +317,9 @@ fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t 
     if (st != FOBF_OK) return st;
   }
   (void)counters;
+  if (rerouted >= 0)
+    return prec_status(FOBF_FP16_STAGE, FOBF_FP16X2_STAGE,
+                       ("fobf_filter_batch: job " + std::to_string(rerouted)).c_str());
   return FOBF_OK;
 }
 

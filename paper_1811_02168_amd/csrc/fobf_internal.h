@@ -42,6 +42,16 @@ void make_params(ImageParams& p, const float* in, float* out, int H, int W,
                  int ld_in, int ld_out, double theta, int K, int T,
                  const double* c);
 
+// Single-word fp16 staging is used only for series whose lowest value over
+// a period is at least -kFp16LobeLimit times their peak (fobf_api.cpp);
+// other FOBF_FP16_STAGE calls run the two-word fp16 kernel instead.
+constexpr double kFp16LobeLimit = 0.01;
+bool fp16_stage_safe(int K, int T, const double* c);
+// The precision a call with `prec` runs in for this series.
+int effective_prec(int prec, int K, int T, const double* c);
+// FOBF_OK when used == requested, else FOBF_WARN_TOL with the reason set.
+fobf_status prec_status(int requested, int used, const char* who);
+
 // Validate fobf_filter arguments; returns FOBF_OK or an error with message.
 fobf_status validate_filter(const float* in, const float* out, int H, int W,
                             int ld_in, int ld_out, double theta, int K, int T,

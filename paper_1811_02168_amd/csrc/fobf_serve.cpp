@@ -333,8 +333,9 @@ void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
     j.theta = q->r.theta;
     j.K = q->r.K;
     j.T = q->T;
-    j.prec = q->r.prec;
+    j.prec = effective_prec(q->r.prec, q->r.K, q->T, q->c);
     for (int k = 0; k < q->r.K; ++k) j.c[k] = q->c[k];
+    q->res.prec = j.prec;
     jobs.push_back(j);
     cdev.push_back(q->c_dev);
     q->res.T = q->T;

@@ -37,7 +37,7 @@ EXPORTS = [
     "fobf_serve_get_stats", "fobf_serve_inject_fault", "fobf_last_error",
     "fobf_version", "fobf_peak", "fobf_fit_period", "fobf_lut_create", "fobf_lut_get",
     "fobf_lut_fit", "fobf_lut_save", "fobf_lut_load", "fobf_lut_destroy",
-    "fobf_filter_workspace_size", "fobf_filter_ws",
+    "fobf_filter_workspace_size", "fobf_filter_ws", "fobf_effective_prec",
 ]
 
 
@@ -82,7 +82,7 @@ class _ServeStats(C.Structure):
 class _Result(C.Structure):
     _fields_ = [("status", C.c_int), ("t_submit", C.c_double),
                 ("t_admit", C.c_double), ("t_start", C.c_double),
-                ("t_done", C.c_double), ("T", C.c_int)]
+                ("t_done", C.c_double), ("T", C.c_int), ("prec", C.c_int)]
 
 
 def _load():
@@ -111,6 +111,7 @@ def _load():
     bind("fobf_filter_ws", [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
                             C.c_double, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
                             C.c_int, C.c_void_p, C.c_size_t, C.c_void_p])
+    bind("fobf_effective_prec", [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)])
     bind("fobf_filter_batch", [C.POINTER(_Job), C.c_int, C.c_void_p,
                                C.c_size_t, C.c_void_p])
     bind("fobf_serve_create", [C.POINTER(_ServeCfg), C.POINTER(C.c_void_p)])
@@ -314,12 +315,23 @@ def filter_workspace_size(H: int, W: int, theta: float, prec="fp32") -> int:
     return n.value
 
 
+def effective_prec(prec, K: int, T: int, c) -> int:
+    """fobf_effective_prec: the precision the filter calls run for ``prec``
+    and the series (K, T, c) (fp16 staging of a series with negative lobes
+    runs as two-word fp16)."""
+    e = lib.fobf_effective_prec(_prec(prec), int(K), int(T), _carr(c, K))
+    if e < 0:
+        raise FobfError(EINVAL, "fobf_effective_prec: invalid arguments")
+    return e
+
+
 def filter(img, theta: float, K: int, T: int, c, prec="fp32", algo="auto",
            out=None, stream=None, workspace=None):
     """fobf_filter on a 2-D float32 CUDA tensor; returns the output tensor.
     Enqueued on ``stream`` (default: torch's current stream).  With
     ``workspace`` (a CUDA tensor of at least filter_workspace_size bytes)
-    the call goes to fobf_filter_ws."""
+    the call goes to fobf_filter_ws.  A WARN_TOL status (fp16 staging run
+    as two-word fp16, see effective_prec) is not an error."""
     import torch
     _check_image(img, "img")
     H, W = img.shape
@@ -343,7 +355,7 @@ def filter(img, theta: float, K: int, T: int, c, prec="fp32", algo="auto",
                                 int(K), int(T), carr, _prec(prec), _algo(algo),
                                 C.c_void_p(workspace.data_ptr()), nbytes,
                                 _stream_ptr(stream))
-    _check(st)
+    _check(st, (OK, WARN_TOL))
     return out
 
 
@@ -413,7 +425,7 @@ def filter_batch(jobs, workspace=None, stream=None):
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
     st = lib.fobf_filter_batch(arr, n, C.c_void_p(workspace.data_ptr()),
                                workspace.numel(), _stream_ptr(stream))
-    _check(st)
+    _check(st, (OK, WARN_TOL))
     return workspace
 
 

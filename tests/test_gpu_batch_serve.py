@@ -245,6 +245,9 @@ def test_serve_mix_equals_alone():
             st, res = srv.poll(t, wait=True)
             assert st == 0, (i, F.last_error())
             assert res.t_submit <= res.t_admit <= res.t_start <= res.t_done
+            f, theta, sigma, K, prec = reqs[i]
+            coef = F.fit(255, sigma, K, eps=0.1)
+            assert res.prec == F.effective_prec(prec, K, coef.T, coef.c)
         stats = srv.stats()
         assert stats["peak_bytes_inflight"] <= budget
         assert stats["peak_inflight"] <= 8
@@ -409,3 +412,41 @@ def test_instruction_rate_probes_are_plausible():
         print("peak", kind, rate)
         assert 0.0 < rate <= 1.1 * peak, (kind, rate)
     assert F.peak("mfma_f32") > 0.5 * 157.3
+
+
+def test_batch_and_serve_run_crude_fp16_series_as_two_word():
+    """fp16 staging of a series with negative lobes (K = 2, sigma = 34)
+    runs as two-word fp16 in the batch launch and in the server too
+    (fobf_effective_prec): the fp16 job equals the same job asked for in
+    two-word fp16 bit for bit, a well-fitted fp16 job in the same batch
+    keeps single-word staging, and the server reports the precision each
+    request ran in."""
+    import torch
+    import paper_1811_02168_amd as F
+    f = workloads.voronoi_image(300, 280, 280, True, 9083).astype(np.float32)
+    crude = F.fit(255, 34.0, 2, eps=1e9)
+    good = F.fit(255, 50.0, 8, eps=1e9)
+    assert F.effective_prec("fp16", 2, crude.T, crude.c) == F.FP16X2_STAGE
+    assert F.effective_prec("fp16", 8, good.T, good.c) == F.FP16_STAGE
+    img = dev_img(f)
+    specs = [(crude, 2, "fp16"), (crude, 2, "fp16x2"), (good, 8, "fp16"), (good, 8, "fp16x2")]
+    outs = [torch.full_like(img, -1.0) for _ in specs]
+    descs = [F.make_job(img, o, 3.0, K, cf.T, cf.c, prec=p) for (cf, K, p), o in zip(specs, outs)]
+    F.filter_batch(descs)
+    torch.cuda.synchronize()
+    o = [x.cpu().numpy() for x in outs]
+    assert np.array_equal(o[0], o[1])
+    assert not np.array_equal(o[2], o[3])          # single-word staging kept
+    ref, num, den = O.fourier_direct(f.astype(np.float64), 3.0, 2, crude.T, crude.c,
+                                     return_nd=True)
+    keep = den / O.blur_weight(*f.shape, 3.0) >= 0.01
+    assert float(np.max(np.abs(o[0] - ref)[keep])) <= 0.05
+    with F.Server(hbm_budget_bytes=1 << 28, max_inflight=4, max_batch=1) as srv:
+        res = []
+        for K, sigma, p in ((2, 34.0, "fp16"), (8, 50.0, "fp16"), (2, 34.0, "fp32")):
+            got = np.full_like(f, np.nan)
+            st, r = srv.poll(srv.submit(f, got, 3.0, sigma, K, prec=p), wait=True)
+            assert st == 0, F.last_error()
+            res.append((r.prec, got))
+    assert [p for p, _ in res] == [F.FP16X2_STAGE, F.FP16_STAGE, F.FP32]
+    assert np.array_equal(res[0][1], o[0])

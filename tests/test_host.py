@@ -122,14 +122,16 @@ def test_fit_invalid_arguments():
 
 def test_filter_workspace_without_device():
     """fobf_filter_workspace_size is host arithmetic: zero where the
-    workspace form is not used (single fp16 below DV = 5, small images, the
-    largest radius class), 8 bytes per pixel of whole tiles otherwise; and
+    workspace form is not used (small images, the largest radius class),
+    8 bytes per pixel of whole tiles otherwise; and
     fobf_filter_ws rejects bad arguments and a missing, short, misaligned or
     overlapping workspace on the host, before any HIP call."""
     import ctypes as C
     import paper_1811_02168_amd as F
     size = F.filter_workspace_size
-    assert size(4096, 4096, 8.0, "fp16") == 0             # single fp16: DV >= 5 only
+    # single fp16 uses the workspace form at DV >= 5 only, but a call may
+    # run as two-word fp16 (a series with negative lobes): sized for that
+    assert size(4096, 4096, 8.0, "fp16") == size(4096, 4096, 8.0, "fp16x2") > 0
     assert size(4096, 4096, 10.0, "fp16") == 8 * 4096 * 4096
     for prec in ("fp32", "bf16", "fp16x2"):
         assert size(1024, 1024, 10.0, prec) == 0            # tiles would be short
@@ -291,3 +293,46 @@ def test_serving_stream_is_a_seeded_replay():
     gaps = np.diff([j.t_arrival for j in a])
     assert np.all(gaps > 0)
     assert 0.5 / 200 < float(np.mean(gaps)) < 2.0 / 200     # ~200 req/s
+
+
+def _series_min_ratio(K, T, c):
+    """Lowest value of the cosine series of eq. (3) over one period,
+    relative to its peak, on a dense grid (independent of the library's
+    sampling)."""
+    t = np.linspace(0.0, T + 0.5, 200001)
+    v = np.cos(2 * np.pi * np.outer(t, np.arange(K)) / (2 * T + 1)) @ np.asarray(c)[:K]
+    return v.min() / v.max()
+
+
+def test_effective_prec_reroutes_series_with_negative_lobes():
+    """fobf_effective_prec: single-word fp16 only for series whose minimum
+    over a period is at least -1% of their peak; every other precision runs
+    as asked.  Checked on the fitted series of the full-size workloads (all
+    kept), on crude fits (small K for their sigma: rerouted), and on
+    two-term series with a closed-form minimum c0 - |c1|."""
+    import paper_1811_02168_amd as F
+    fp16, fp16x2 = F.fobf.FP16_STAGE, F.fobf.FP16X2_STAGE
+    cases = [(20.0, 8), (50.0, 8), (100.0, 8), (30.0, 6), (80.0, 6), (100.0, 4),
+             (34.0, 2), (10.0, 6), (10.0, 4), (15.0, 4), (10.0, 8)]
+    for sigma, K in cases:
+        ref = O.fit(255, sigma, K)
+        ratio = _series_min_ratio(K, ref["T"], ref["c"])
+        want = fp16 if ratio >= -0.01 else fp16x2
+        assert abs(ratio + 0.01) > 2e-3, (sigma, K, ratio)    # clear of the threshold
+        assert F.effective_prec("fp16", K, ref["T"], ref["c"]) == want, (sigma, K, ratio)
+        for p in ("fp32", "bf16", "fp16x2"):
+            assert F.effective_prec(p, K, ref["T"], ref["c"]) == F.fobf._PREC[p]
+    # the paper's workloads keep fp16; the crude fits do not
+    assert F.effective_prec("fp16", 8, *[O.fit(255, 50.0, 8)[k] for k in ("T", "c")]) == fp16
+    assert F.effective_prec("fp16", 2, *[O.fit(255, 34.0, 2)[k] for k in ("T", "c")]) == fp16x2
+    # two terms: min = c0 - |c1| (t = T + 1/2 gives cos = -1 for k = 1)
+    assert F.effective_prec("fp16", 2, 40, [0.5, 0.5]) == fp16            # min 0
+    assert F.effective_prec("fp16", 2, 40, [0.5, 0.51]) == fp16           # min -0.0099 peak
+    assert F.effective_prec("fp16", 2, 40, [0.5, 0.52]) == fp16x2         # min -0.0196 peak
+    assert F.effective_prec("fp16", 1, 7, [-1.0]) == fp16x2               # no positive peak
+    import ctypes as C
+    arr = (C.c_double * 32)(0.5, 0.5)
+    assert F.lib.fobf_effective_prec(9, 2, 40, arr) == -1
+    assert F.lib.fobf_effective_prec(1, 0, 40, arr) == -1
+    assert F.lib.fobf_effective_prec(1, 2, 0, arr) == -1
+    assert F.lib.fobf_effective_prec(1, 2, 40, None) == -1
