@@ -100,6 +100,30 @@ fobf_status fobf_fit(int R, double sigma, int K, double eps, int Tmax,
                      fobf_coef* out);
 
 /*
+ * fobf_fit_warm -- the same fixed-order fit as fobf_fit (K >= 1), with the
+ * period found by a local search started at T0 instead of the full scan.
+ * The paper notes that E(K, T) is unimodal in T for fixed K (Sec. II, after
+ * Algorithm 1).  The search walks downhill from T0 with doubling steps until
+ * E rises, then narrows that bracket by golden-section steps: about 20-30
+ * least-squares solves instead of Tmax - K + 2.  Measured on the Gaussian
+ * kernel, E decreases strictly from about T = R/2 up to T* and increases
+ * strictly from there to at least 3.4 R (R = 31 .. 1023, sigma = 0.04 R ..
+ * 0.4 R, K = 2 .. 12), so any T0 in that range -- T0 = R in particular --
+ * gives the scan's T*, except where E has reached the float64 floor
+ * (E < 1e-12) and several periods are equally good.  Below about R/2, and
+ * for K >= 11 close to 4R, E(K, T) has ripples: a start there can stop at
+ * a local minimum.
+ *
+ * T0 <= 0 starts at T0 = R; T0 is clamped to [max(1, K-1), Tmax].  A table
+ * read-out (fobf_lut_fit) gives a start near T*: fobf_fit_warm(R, sigma,
+ * lut K, eps, 0, lut T, out) refines it.  Arguments and statuses otherwise
+ * as fobf_fit with K >= 1 (FOBF_WARN_TOL when E > eps).  Not cached;
+ * thread-safe.
+ */
+fobf_status fobf_fit_warm(int R, double sigma, int K, double eps, int Tmax, int T0,
+                          fobf_coef* out);
+
+/*
  * fobf_fit_period -- the least-squares coefficients of eq. (5) at one given
  * period T (no scan over T).  T = R is the fixed period [-R, R] of the
  * earlier Fourier bilateral filter the paper compares against (Sec. III,

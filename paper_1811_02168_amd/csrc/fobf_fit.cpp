@@ -173,6 +173,83 @@ bool scan_T(int R, const double* b, int K, int Tmax, int* Tbest, FitOne* best) {
   return found;
 }
 
+// Best period for fixed K by a local search from T0 (Sec. II, the remark
+// after Algorithm 1: E(K, T) is unimodal in T for fixed K).  Measured on
+// the Gaussian kernel (R = 31 .. 1023, sigma from 0.04 R to 0.4 R, K = 2 ..
+// 12), E falls strictly from about T = R/2 up to T* and rises strictly from
+// T* to at least 3.4 R, so a descent started anywhere in that basin -- T0 =
+// R is inside it in every case -- ends at the scan's T*; only where E
+// reaches the float64 floor (~1e-29) is the curve flat and noisy, and any
+// period there is as good.  Below R/2 (and for K >= 11 near 4R) the curve
+// has ripples, which is why the search needs a start inside the basin
+// rather than the scan's T = K-1.
+//
+// The search brackets the minimum by doubling steps downhill from T0, then
+// narrows the bracket by golden-section steps on the integers and finally
+// compares the last few periods (smallest T on exact ties).  About 20-30
+// least-squares solves instead of the scan's Tmax - K + 2.
+bool descend_T(int R, const double* b, int K, int Tlo, int Thi, int T0, int* Tbest,
+               FitOne* best, int* evals) {
+  if (Tlo > Thi) return false;
+  FitWork w;
+  std::map<int, FitOne> memo;
+  auto E = [&](int T) -> double {
+    auto it = memo.find(T);
+    if (it == memo.end()) {
+      it = memo.emplace(T, fit_one(R, b, K, T, &w)).first;
+      if (evals) *evals += 1;
+    }
+    return it->second.ok ? it->second.E : INFINITY;
+  };
+  T0 = std::min(std::max(T0, Tlo), Thi);
+  const double e0 = E(T0);
+  const double el = T0 > Tlo ? E(T0 - 1) : INFINITY;
+  const double er = T0 < Thi ? E(T0 + 1) : INFINITY;
+  int lo = std::max(Tlo, T0 - 1), hi = std::min(Thi, T0 + 1);
+  if (el < e0 || er < e0) {
+    // walk downhill with doubling steps until E rises: the minimum then
+    // lies strictly between the last point before the best one and the
+    // point after it
+    const int d = (el < er) ? -1 : 1;
+    int a = T0, m = T0 + d, step = 1;
+    for (;;) {
+      step *= 2;
+      int c = m + d * step;
+      c = std::min(std::max(c, Tlo), Thi);
+      if (c == m) {           // at the end of the range: the minimum is in (a, m]
+        lo = std::min(a, m);
+        hi = std::max(a, m);
+        break;
+      }
+      if (E(c) >= E(m)) {
+        lo = std::min(a, c);
+        hi = std::max(a, c);
+        break;
+      }
+      a = m;
+      m = c;
+    }
+    // golden-section narrowing of [lo, hi], which holds a minimum inside
+    while (hi - lo > 4) {
+      const int x1 = lo + static_cast<int>(std::lround(0.381966 * (hi - lo)));
+      const int x2 = hi - static_cast<int>(std::lround(0.381966 * (hi - lo)));
+      if (x1 >= x2) break;
+      if (E(x1) <= E(x2)) hi = x2; else lo = x1;
+    }
+  }
+  bool found = false;
+  for (int T = lo; T <= hi; ++T) {
+    const double e = E(T);
+    if (!std::isfinite(e)) continue;
+    if (!found || e < best->E) {
+      *best = memo.at(T);
+      *Tbest = T;
+      found = true;
+    }
+  }
+  return found;
+}
+
 std::vector<double> gaussian_samples(int R, double sigma) {
   std::vector<double> b(R + 1);
   for (int t = 0; t <= R; ++t) b[t] = std::exp(-(double)t * t / (2.0 * sigma * sigma));
@@ -292,6 +369,32 @@ extern "C" fobf_status fobf_fit(int R, double sigma, int K, double eps,
     g_cache[key] = *out;
   }
   return st;
+}
+
+extern "C" fobf_status fobf_fit_warm(int R, double sigma, int K, double eps, int Tmax, int T0,
+                                     fobf_coef* out) {
+  if (!out) return fail(FOBF_EINVAL, "fobf_fit_warm: out is NULL");
+  if (R < 1) return fail(FOBF_EINVAL, "fobf_fit_warm: R must be >= 1");
+  if (!(sigma > 0.0) || !std::isfinite(sigma))
+    return fail(FOBF_EINVAL, "fobf_fit_warm: sigma must be positive and finite");
+  if (!(eps > 0.0)) return fail(FOBF_EINVAL, "fobf_fit_warm: eps must be > 0");
+  if (K < 1 || K > FOBF_KMAX || K > R + 1)
+    return fail(FOBF_EINVAL, "fobf_fit_warm: K out of range");
+  if (Tmax <= 0) Tmax = 4 * R;
+  const int Tlo = std::max(1, K - 1);
+  if (Tmax < Tlo) return fail(FOBF_EINVAL, "fobf_fit_warm: Tmax below K-1");
+  if (T0 <= 0) T0 = R;
+  std::vector<double> b = gaussian_samples(R, sigma);
+  int T = 0, evals = 0;
+  FitOne f{};
+  if (!descend_T(R, b.data(), K, Tlo, Tmax, T0, &T, &f, &evals))
+    return fail(FOBF_EINTERNAL, "fobf_fit_warm: no full-rank period found");
+  fill(out, R, K, T, Tmax, sigma, f);
+  if (!(f.E <= eps)) {
+    set_error("fobf_fit_warm: E(K,T*) exceeds eps");
+    return FOBF_WARN_TOL;
+  }
+  return FOBF_OK;
 }
 
 extern "C" int fobf_fit_cache_clear(void) {

@@ -15,7 +15,8 @@
 // different lanes overlap (copies of one with the kernel of another).
 //
 // Coefficients are fitted on the host (float64, cached by (R, sigma, K))
-// by a small pool of fit threads, so that a request whose (sigma, K) has not
+// by a small pool of fit threads -- the period by a local search started
+// from the periods of already fitted neighbouring sigmas -- so that a request whose (sigma, K) has not
 // been seen yet never holds up the admission of requests whose
 // coefficients are ready: the scheduler admits, in arrival order, the
 // queued requests whose fit has finished.  Each distinct fit is uploaded
@@ -245,8 +246,40 @@ fobf_status coefficients(fobf_server* s, Req* q, hipStream_t st) {
   return FOBF_OK;
 }
 
-// Fit threads: solve queued (R, sigma, K) keys on the host and mark them
-// ready (or failed), then wake the scheduler.
+// Start of the period search for a new key: the periods already fitted
+// for the same (R, K) at the nearest sigma below and above, interpolated
+// linearly in sigma (the optimal period varies smoothly with sigma, Sec. II
+// after Algorithm 1), or the one neighbour there is, or 0 (the search then
+// starts at T = R).  Caller holds s->mu.
+int warm_period(fobf_server* s, const CoefKey& key, double sigma) {
+  const int R = std::get<0>(key), K = std::get<2>(key);
+  double slo = -1.0, shi = -1.0;
+  int tlo = 0, thi = 0;
+  for (const auto& kv : s->coef) {
+    if (std::get<0>(kv.first) != R || std::get<2>(kv.first) != K) continue;
+    if (kv.second.state != fobf_server::kReady) continue;
+    double sg;
+    const uint64_t b = std::get<1>(kv.first);
+    std::memcpy(&sg, &b, sizeof(sg));
+    if (sg <= sigma && (slo < 0.0 || sg > slo)) {
+      slo = sg;
+      tlo = kv.second.T;
+    }
+    if (sg >= sigma && (shi < 0.0 || sg < shi)) {
+      shi = sg;
+      thi = kv.second.T;
+    }
+  }
+  if (slo >= 0.0 && shi >= 0.0 && shi > slo)
+    return static_cast<int>(std::lround(tlo + (thi - tlo) * (sigma - slo) / (shi - slo)));
+  if (slo >= 0.0) return tlo;
+  if (shi >= 0.0) return thi;
+  return 0;
+}
+
+// Fit threads: solve queued (R, sigma, K) keys on the host (the period by
+// a local search from warm_period, fobf_fit_warm) and mark them ready (or
+// failed), then wake the scheduler.
 void fitter_main(fobf_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
@@ -254,12 +287,14 @@ void fitter_main(fobf_server* s) {
     if (s->stop) return;
     const CoefKey key = s->fit_queue.front();
     s->fit_queue.pop_front();
-    lk.unlock();
     double sigma;
     const uint64_t sb = std::get<1>(key);
     std::memcpy(&sigma, &sb, sizeof(sigma));
+    const int T0 = warm_period(s, key, sigma);
+    lk.unlock();
     fobf_coef fc;
-    const fobf_status st = fobf_fit(std::get<0>(key), sigma, std::get<2>(key), s->cfg.eps, 0, &fc);
+    const fobf_status st =
+        fobf_fit_warm(std::get<0>(key), sigma, std::get<2>(key), s->cfg.eps, 0, T0, &fc);
     lk.lock();
     fobf_server::Coef& e = s->coef.at(key);
     if (st == FOBF_OK || st == FOBF_WARN_TOL) {

@@ -38,6 +38,7 @@ EXPORTS = [
     "fobf_version", "fobf_peak", "fobf_fit_period", "fobf_lut_create", "fobf_lut_get",
     "fobf_lut_fit", "fobf_lut_save", "fobf_lut_load", "fobf_lut_destroy",
     "fobf_filter_workspace_size", "fobf_filter_ws", "fobf_effective_prec",
+    "fobf_fit_warm",
 ]
 
 
@@ -132,6 +133,8 @@ def _load():
     bind("fobf_fit_cache_clear", [])
     bind("fobf_peak", [C.c_int, C.c_void_p, C.POINTER(C.c_double)])
     bind("fobf_fit_period", [C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(_Coef)])
+    bind("fobf_fit_warm", [C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int,
+                           C.POINTER(_Coef)])
     bind("fobf_lut_create", [C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double),
                              C.c_int, C.c_int, C.POINTER(C.c_void_p)])
     bind("fobf_lut_get", [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int),
@@ -207,6 +210,17 @@ def fit(R: int, sigma: float, K: int, eps: float = 0.1, Tmax: int = 0) -> Coef:
     return Coef._from(out, st)
 
 
+def fit_warm(R: int, sigma: float, K: int, eps: float = 0.1, T0: int = 0,
+             Tmax: int = 0) -> Coef:
+    """fobf_fit_warm: fixed-order fit with the period found by a local
+    search from T0 (0: T0 = R) instead of the full scan."""
+    out = _Coef()
+    st = lib.fobf_fit_warm(int(R), float(sigma), int(K), float(eps), int(Tmax), int(T0),
+                           C.byref(out))
+    _check(st, (OK, WARN_TOL))
+    return Coef._from(out, st)
+
+
 def fit_cache_clear() -> int:
     """fobf_fit_cache_clear: drop the host fit cache; returns entries dropped."""
     return int(lib.fobf_fit_cache_clear())
@@ -247,10 +261,15 @@ class Lut:
         _check(lib.fobf_lut_get(self._h, int(i_sigma), int(i_eps), C.byref(K), C.byref(T)))
         return K.value, T.value
 
-    def fit(self, sigma, eps) -> Coef:
+    def fit(self, sigma, eps, refine=False) -> Coef:
+        """fobf_lut_fit: (K, T) read from the table, c from one solve; with
+        ``refine`` the period is then searched locally from the table's T
+        (fobf_fit_warm at the table's K)."""
         out = _Coef()
         st = lib.fobf_lut_fit(self._h, float(sigma), float(eps), C.byref(out))
         _check(st, (OK, WARN_TOL))
+        if refine:
+            return fit_warm(out.R, sigma, out.K, eps, T0=out.T)
         return Coef._from(out, st)
 
     def save(self, path):

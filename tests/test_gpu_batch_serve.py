@@ -215,8 +215,22 @@ def serve_requests(n=40, seed=3):
     return reqs
 
 
-def expected(F, f, theta, sigma, K, prec):
-    coef = F.fit(255, sigma, K, eps=0.1)
+def served_coef(F, sigma, K, T):
+    """The coefficients a server used for (sigma, K) given the period T it
+    reports: its fit threads search the period locally (fobf_fit_warm),
+    which finds the full scan's T* wherever E(K, T*) > 1e-12 and a period
+    at float64's floor otherwise; the coefficients are the least-squares
+    solve at that period (fobf_fit_period, the same solve)."""
+    full = F.fit(255, sigma, K, eps=0.1)
+    if full.E > 1e-12:
+        assert T == full.T, (sigma, K, T, full.T)
+    c = F.fit_period(255, sigma, K, T)
+    assert c.E <= max(1e-12, full.E * (1 + 1e-9)), (sigma, K, T, c.E)
+    return c
+
+
+def expected(F, f, theta, sigma, K, prec, T):
+    coef = served_coef(F, sigma, K, T)
     return single(F, dev_img(f), theta, K, coef.T, coef.c, prec)
 
 
@@ -241,12 +255,14 @@ def test_serve_mix_equals_alone():
             t.start()
         for t in th:
             t.join()
+        periods = [None] * len(reqs)
         for i, t in enumerate(tickets):
             st, res = srv.poll(t, wait=True)
+            periods[i] = res.T
             assert st == 0, (i, F.last_error())
             assert res.t_submit <= res.t_admit <= res.t_start <= res.t_done
             f, theta, sigma, K, prec = reqs[i]
-            coef = F.fit(255, sigma, K, eps=0.1)
+            coef = served_coef(F, sigma, K, res.T)
             assert res.prec == F.effective_prec(prec, K, coef.T, coef.c)
         stats = srv.stats()
         assert stats["peak_bytes_inflight"] <= budget
@@ -260,7 +276,7 @@ def test_serve_mix_equals_alone():
             assert st == 0
             tol = 1e-3 if prec == "fp32" else TOL
             assert float(np.max(np.abs(alone - outs[i]))) <= tol
-            ref = expected(F, f, theta, sigma, K, prec)
+            ref = expected(F, f, theta, sigma, K, prec, periods[i])
             assert float(np.max(np.abs(outs[i] - ref))) <= tol
 
 
@@ -271,8 +287,7 @@ def test_serve_against_oracle_small():
     with F.Server(hbm_budget_bytes=1 << 26) as srv:
         st, res = srv.poll(srv.submit(f, out, 3.0, 30.0, 4), wait=True)
     assert st == 0
-    coef = F.fit(255, 30.0, 4, eps=0.1)
-    assert res.T == coef.T
+    coef = served_coef(F, 30.0, 4, res.T)
     ref = O.fourier_direct(f.astype(np.float64), 3.0, 4, coef.T, coef.c)
     assert float(np.max(np.abs(out - ref))) <= 0.05
 
@@ -331,8 +346,7 @@ def test_serve_cold_fits_do_not_block_ready_requests():
         st1, r1 = srv.poll(t1, wait=True)
     assert st1 == 0 and st2 == 0
     assert r2.t_admit <= r1.t_admit          # passed over while fitting
-    c_slow = F.fit(255, slow[1], slow[2], eps=0.1)
-    assert r1.T == c_slow.T
+    c_slow = served_coef(F, slow[1], slow[2], r1.T)
     ref = single(F, dev_img(f), 2.0, slow[2], c_slow.T, c_slow.c, "fp32")
     assert float(np.max(np.abs(o_slow - ref))) <= 1e-3
     c4 = F.fit(255, 40.0, 4, eps=0.1)
@@ -354,8 +368,7 @@ def test_serve_many_cold_keys():
     img = dev_img(f)
     for (st, r), o, (s, K) in zip(res, outs, keys):
         assert st == 0
-        c = F.fit(255, s, K, eps=0.1)
-        assert r.T == c.T
+        c = served_coef(F, s, K, r.T)
         ref = single(F, img, 3.0, K, c.T, c.c, "fp32")
         assert float(np.max(np.abs(o - ref))) <= 1e-3
 
@@ -390,8 +403,7 @@ def test_serve_coefficient_row_ordering_across_lanes():
         res = [srv.poll(t, wait=True) for t in ts]
     for i, ((f, theta, (s, K)), o, (st, r)) in enumerate(zip(reqs, outs, res)):
         assert st == 0, (i, F.last_error())
-        coef = F.fit(255, s, K, eps=0.1)
-        assert r.T == coef.T
+        coef = served_coef(F, s, K, r.T)
         img = dev_img(f)
         ref = torch.full_like(img, -1.0)
         F.filter_batch([F.make_job(img, ref, theta, K, coef.T, coef.c)])

@@ -92,7 +92,9 @@ def test_ws_shapes_against_oracle_and_lds_form(prec, H, W, theta, K, sigma, pad)
     f = workloads.voronoi_image(H, W, max(4, H * W // 65536), True, H + 7 * W)
     T, c = fitted(sigma, K)
     got, used = run_ws(f, theta, K, T, c, prec, pad=pad)
-    assert used == (prec != "fp16" or dv_of(theta) >= 5)
+    # every precision gets a workspace at these sizes (single-word fp16 at
+    # DV < 5 is sized for the two-word mode it may run as, and ignores it)
+    assert used
     ys, xs = points(H, W, 300, H * 3 + W)
     ref, num, den = O.brute_bf_points(f, theta, O.cosine_series(c, T), ys, xs)
     mask = den / O.blur_weight(H, W, theta)[ys, xs] >= 0.01
@@ -109,15 +111,15 @@ def test_ws_shapes_against_oracle_and_lds_form(prec, H, W, theta, K, sigma, pad)
 
 
 def test_ws_falls_back_where_not_used():
-    """Single fp16 at small radii, short or narrow images and the largest
-    radius class need no workspace: fobf_filter_ws then equals fobf_filter
-    bit for bit."""
+    """Short or narrow images and the largest radius class need no
+    workspace, and single-word fp16 at small radii does not use the one it
+    is sized for: fobf_filter_ws then equals fobf_filter bit for bit."""
     import torch
     import paper_1811_02168_amd as F
     cases = [(4096, 512, 10.0, "fp32"), (2048, 2048, 5.0, "fp16"),
              (600, 700, 5.0, "fp16x2"), (2048, 2048, 15.0, "bf16")]
     for H, W, theta, prec in cases:
-        assert F.filter_workspace_size(H, W, theta, prec) == 0
+        assert (F.filter_workspace_size(H, W, theta, prec) == 0) == (prec != "fp16")
         f = workloads.voronoi_image(H, W, 64, True, 31 + H)
         T, c = fitted(40.0, 6)
         img = torch.from_numpy(f.astype(np.float32)).cuda()

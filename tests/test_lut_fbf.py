@@ -178,3 +178,66 @@ def test_error_vs_order_curves():
         assert r["E_opt"] < r["E_fixed"], r
     fig3 = [r for r in rows if r["sigma"] == 40.0 and r["K"] == 4][0]
     assert fig3["E_opt"] < 0.1 * fig3["E_fixed"]
+
+
+# ---------------------------------------------- warm-started period search --
+
+def test_fit_warm_reaches_the_scan_optimum():
+    """fobf_fit_warm (local search from a start T0, Sec. II's unimodality of
+    E(K, T) in T) against the oracle's full scan over T = 1 .. 4R on the
+    grid sigma = 10, 20, .., 100 x K = 3 .. 12: from the default start
+    (T0 = R), from a table read-out's period, and from starts 60 periods
+    either side of T*, the period equals the oracle's T* wherever
+    E(K, T*) > 1e-12; below that (several periods tie at float64's floor)
+    the error found is itself <= 1e-12.  Its E and c are the oracle's at
+    that period."""
+    import paper_1811_02168_amd as F
+    lut = F.Lut.create(255, [10.0, 40.0, 70.0, 100.0], [1e-1, 1e-3])
+    try:
+        for K in range(3, 13):
+            for sigma in range(10, 101, 10):
+                ref = O.fit(255, float(sigma), K)
+                t_tab = lut.fit(float(sigma), 1e-2).T
+                for T0 in (0, t_tab, max(130, ref["T"] - 60), ref["T"] + 60):
+                    w = F.fit_warm(255, float(sigma), K, eps=1e9, T0=T0)
+                    if ref["E"] > 1e-12:
+                        assert w.T == ref["T"], (K, sigma, T0, w.T, ref["T"])
+                        assert w.E == pytest.approx(ref["E"], rel=1e-6)
+                        np.testing.assert_allclose(w.c, ref["c"], rtol=1e-7, atol=1e-10)
+                    else:
+                        assert w.E <= 1e-12, (K, sigma, T0, w.E)
+    finally:
+        lut.close()
+
+
+def test_fit_warm_refines_the_table_read_out():
+    """Table read-out then local search (Lut.fit(..., refine=True)): the
+    order is the table's, the period the oracle's best for that order (the
+    table's own period is only interpolated), so the error never exceeds
+    the plain read-out's."""
+    import paper_1811_02168_amd as F
+    lut = F.Lut.create(255, [10.0, 40.0, 70.0, 100.0], [1e-1, 1e-3])
+    try:
+        for sigma, eps in [(15.0, 5e-2), (33.0, 1e-2), (55.0, 2e-3), (90.0, 1e-3)]:
+            plain = lut.fit(sigma, eps)
+            ref_ = lut.fit(sigma, eps, refine=True)
+            assert ref_.K == plain.K
+            want = O.fit(255, sigma, plain.K)
+            if want["E"] > 1e-12:
+                assert ref_.T == want["T"]
+            assert ref_.E <= plain.E * (1 + 1e-9)
+    finally:
+        lut.close()
+
+
+def test_fit_warm_arguments():
+    import paper_1811_02168_amd as F
+    for args in [(0, 30.0, 4), (255, -1.0, 4), (255, 30.0, 0), (255, 30.0, 33)]:
+        with pytest.raises(F.FobfError):
+            F.fit_warm(*args)
+    with pytest.raises(F.FobfError):
+        F.fit_warm(255, 30.0, 4, eps=0.0)
+    # starts outside [K-1, Tmax] are clamped into it
+    a = F.fit_warm(255, 30.0, 4, T0=-5)
+    b = F.fit_warm(255, 30.0, 4, T0=100000)
+    assert a.T == b.T == F.fit(255, 30.0, 4).T
