@@ -267,6 +267,30 @@ fobf_status fobf_filter_ws(const float* d_in, float* d_out, int H, int W, int ld
                            int prec, int algo, void* d_work, size_t work_bytes,
                            void* hip_stream);
 
+/*
+ * fobf_filter_ws_static -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): fobf_filter_ws with its workspace taken from a device array
+ * the library holds instead of a caller buffer.  Arguments, validation,
+ * outputs and statuses are those of fobf_filter_ws (bit-identical output);
+ * the call allocates nothing and enqueues kernels only.
+ *
+ * The array holds FOBF_STATIC_SCRATCH_BYTES (128 MiB: N and D of one
+ * 4096 x 4096 image); an image whose fobf_filter_workspace_size exceeds it
+ * is rejected with FOBF_EINVAL before any device work.  Each GPU holds its
+ * own copy from the first call on it (made with that GPU current; the
+ * stream must belong to the calling thread's current device) until the
+ * process ends.  Every call on one GPU shares that GPU's copy and leaves
+ * the last call's partial sums in it: calls whose work overlaps on one GPU
+ * (two streams, or two threads) race and must be ordered by the caller.
+ * Nothing in it needs clearing: each tile writes its N and D before reading
+ * them.
+ */
+#define FOBF_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+fobf_status fobf_filter_ws_static(const float* d_in, float* d_out, int H, int W, int ld_in,
+                                  int ld_out, double theta, int K, int T, const double* c,
+                                  int prec, int algo, void* hip_stream);
+
 /* One image of a batch (all pointers device pointers, caller-owned). */
 typedef struct {
   const float* d_in;

@@ -24,6 +24,7 @@ SOURCES = [
     "fobf_valu.hip",
     "fobf_mfma.hip",
     "fobf_mfma_ws.hip",
+    "fobf_static.hip",
     "fobf_batch.hip",
     "fobf_tune.hip",
     "fobf_serve.cpp",

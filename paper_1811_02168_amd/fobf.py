@@ -38,8 +38,10 @@ EXPORTS = [
     "fobf_version", "fobf_peak", "fobf_fit_period", "fobf_lut_create", "fobf_lut_get",
     "fobf_lut_fit", "fobf_lut_save", "fobf_lut_load", "fobf_lut_destroy",
     "fobf_filter_workspace_size", "fobf_filter_ws", "fobf_effective_prec",
-    "fobf_fit_warm",
+    "fobf_filter_ws_static", "fobf_fit_warm",
 ]
+
+STATIC_SCRATCH_BYTES = 128 << 20     # FOBF_STATIC_SCRATCH_BYTES
 
 
 class FobfError(RuntimeError):
@@ -113,6 +115,9 @@ def _load():
                             C.c_double, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
                             C.c_int, C.c_void_p, C.c_size_t, C.c_void_p])
     bind("fobf_effective_prec", [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)])
+    bind("fobf_filter_ws_static", [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_double, C.c_int, C.c_int,
+                                   C.POINTER(C.c_double), C.c_int, C.c_int, C.c_void_p])
     bind("fobf_filter_batch", [C.POINTER(_Job), C.c_int, C.c_void_p,
                                C.c_size_t, C.c_void_p])
     bind("fobf_serve_create", [C.POINTER(_ServeCfg), C.POINTER(C.c_void_p)])
@@ -374,6 +379,27 @@ def filter(img, theta: float, K: int, T: int, c, prec="fp32", algo="auto",
                                 int(K), int(T), carr, _prec(prec), _algo(algo),
                                 C.c_void_p(workspace.data_ptr()), nbytes,
                                 _stream_ptr(stream))
+    _check(st, (OK, WARN_TOL))
+    return out
+
+
+def filter_ws_static(img, theta: float, K: int, T: int, c, prec="fp32", algo="auto",
+                     out=None, stream=None):
+    """fobf_filter_ws_static: fobf_filter_ws with the library's static
+    device scratch as the workspace (allocates nothing; images whose
+    workspace exceeds STATIC_SCRATCH_BYTES are rejected).  ``out`` must be
+    given: this call allocates no device memory, not even for the result."""
+    _check_image(img, "img")
+    if out is None:
+        raise ValueError("filter_ws_static allocates nothing: pass out")
+    _check_image(out, "out")
+    H, W = img.shape
+    if tuple(out.shape) != (H, W):
+        raise ValueError("out shape mismatch")
+    st = lib.fobf_filter_ws_static(C.c_void_p(img.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   H, W, img.stride(0), out.stride(0), float(theta),
+                                   int(K), int(T), _carr(c, K), _prec(prec), _algo(algo),
+                                   _stream_ptr(stream))
     _check(st, (OK, WARN_TOL))
     return out
 
