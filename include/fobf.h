@@ -242,16 +242,17 @@ int fobf_effective_prec(int prec, int K, int T, const double* c);
  * so far fewer of the vertical pass's halo rows are recomputed, and lets
  * FOBF_FP32 stage each block's channels once per workgroup instead of once
  * per wave (its output is then identical to fobf_filter's, bit for bit).
- * FOBF_FP32 and the two-word modes (FOBF_BF16_STAGE, FOBF_FP16X2_STAGE) use
- * it for images tall enough to give such tiles while still filling the
- * device (e.g. 2048^2 and larger at theta <= 13.5), FOBF_FP16_STAGE for
- * those at 8.7 < theta <= 13.5.  For every other case the workspace is not
- * used and fobf_filter_ws behaves exactly as fobf_filter.
+ * Every precision uses it for images tall enough to give such tiles while
+ * still filling the device (e.g. 2048^2 and larger at theta <= 13.5); there
+ * FOBF_FP16_STAGE also folds two frequencies per pass over the tile (N and
+ * D make half the round trips; same output as one at a time).  For every
+ * other case the workspace is not used and fobf_filter_ws behaves exactly
+ * as fobf_filter.
  *
  * fobf_filter_workspace_size: *bytes = the workspace fobf_filter_ws needs
  *   for an H x W image at this theta and precision (0: none; about 8 bytes
- *   per pixel otherwise; for FOBF_FP16_STAGE, what FOBF_FP16X2_STAGE needs,
- *   since such a call may run in that mode).  Host-only, no device work.
+ *   per pixel otherwise, the same for every precision).  Host-only, no
+ *   device work.
  *   Validates H, W >= 0, theta, prec and bytes != NULL (FOBF_EINVAL).
  * fobf_filter_ws: arguments as fobf_filter, plus d_work (device memory, 4-
  *   byte aligned, overlapping neither image) of work_bytes >=

@@ -171,9 +171,9 @@ extern "C" fobf_status fobf_filter_workspace_size(int H, int W, double theta, in
   p.H = H;
   p.W = W;
   p.r = r;
-  // FOBF_FP16_STAGE may run as FOBF_FP16X2_STAGE (effective_prec), whose
-  // workspace form covers more radius classes: size for that
-  *bytes = ws_bytes(p, prec == FOBF_FP16_STAGE ? FOBF_FP16X2_STAGE : prec);
+  // (every precision's workspace form has the same tiles, so a
+  // FOBF_FP16_STAGE call that runs as FOBF_FP16X2_STAGE fits it too)
+  *bytes = ws_bytes(p, prec);
   return FOBF_OK;
 }
 

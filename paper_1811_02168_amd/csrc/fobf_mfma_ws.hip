@@ -114,17 +114,18 @@ fobf_status launch_staged_ws(const ImageParams& p, int DV, int nblk, float* work
 }  // namespace
 
 // Tile height (16-row blocks) of the workspace forms, or 0 where they are
-// not used: float32 and the two-word modes (whose LDS otherwise caps the
-// tiles at 128 and 96 rows) at radius classes DV = 2..6 (eight strips),
-// single-word fp16 at DV = 5..6 only (measured at 4096^2: theta 10 and 12
-// 9% and 17% faster, theta 8 equal, theta 5 5% slower), and only when the
-// image is tall enough for tiles of at least 8 blocks while still giving
-// about one workgroup per compute unit (256 on the MI355X).  At most 32
-// blocks.
+// not used: every precision (the LDS otherwise caps the tiles at 128 rows
+// for float32 and single-word fp16, 96 for the two-word modes) at radius
+// classes DV = 2..6 (eight strips), and only when the image is tall enough
+// for tiles of at least 8 blocks while still giving about one workgroup per
+// compute unit (256 on the MI355X).  At most 32 blocks.  (Single-word fp16
+// folds two frequencies per pass there; measured at 4096^2, K = 8 its
+// workspace form takes 0.37 / 0.40 / 0.45 / 0.52 ms at theta = 5 / 8 / 10 /
+// 12 against 0.47 / 0.53 / 0.62 / 0.80 ms for the LDS form.)
 int ws_nblk(const ImageParams& p, int prec) {
   if (prec < FOBF_FP32 || prec > FOBF_FP16X2_STAGE) return 0;
   const int DV = (MSTRIP + 2 * p.r + 15) / 16;
-  if (DV < (prec == FOBF_FP16_STAGE ? 5 : 2) || DV > 6 || p.H < 1 || p.W < 1) return 0;
+  if (DV < 2 || DV > 6 || p.H < 1 || p.W < 1) return 0;
   const long ntx = (p.W + kWsWaves * MSTRIP - 1) / (kWsWaves * MSTRIP);
   const long rows = (p.H + 15) / 16;
   const long nty_target = (256 + ntx - 1) / ntx;

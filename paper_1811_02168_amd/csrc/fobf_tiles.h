@@ -474,6 +474,24 @@ __host__ __device__ constexpr int stage_pitch(int cw) { return ((cw + 39) / 64) 
 __host__ __device__ constexpr int stage_cols(int shs, int nw) { return 16 * (nw - 1) + 32 * shs; }
 constexpr int STAGE_CH = 4;   // channels per staged buffer (per word part)
 
+// Channel groups of one pass over a tile.  A group is {f} (k = 0, no trig),
+// one frequency k (C_k f, S_k f, C_k, S_k), f with frequency 1 (5 channels)
+// or two frequencies k, k+1 (8 channels): G = [f] + 4 NF.  The workspace
+// form of single-word fp16 merges groups that way, so that N and D make 4
+// instead of 8 round trips through the workspace at K = 8 and the fold's
+// pixel values are fetched once per two frequencies; it then stages eight
+// channels per buffer.  Each channel's products and each pixel's sequence
+// of additions into N and D are those of one-frequency groups, so the
+// output is unchanged bit for bit.  The other forms stage four channels.
+template <int G>
+constexpr bool group_has_f() { return G % 4 == 1; }
+template <int G>
+constexpr int group_freqs() { return G / 4; }
+template <typename OT, bool GND>
+constexpr bool staged_merge() { return GND && Stage<OT>::kParts == 1; }
+template <typename OT, bool GND>
+constexpr int staged_channels() { return staged_merge<OT, GND>() ? 8 : STAGE_CH; }
+
 // Staging items: IW consecutive columns of one row of a 16-row block, one
 // item per thread.  Only the CWn = 16 NW + 2r columns that meet non-zero
 // taps are built (the tail stays as zeroed at tile start).  With r <= 8 (DV
@@ -510,7 +528,7 @@ constexpr int staged_bufs() { return GND ? 2 : 1; }
 template <typename OT, int DV, int NW, bool GND = false>
 constexpr size_t staged_stage_bytes() {
   return sizeof(typename Stage<OT>::T) * staged_bufs<OT, NW, GND>() * Stage<OT>::kParts *
-         STAGE_CH * 16 * stage_pitch(stage_width<DV, NW>());
+         staged_channels<OT, GND>() * 16 * stage_pitch(stage_width<DV, NW>());
 }
 
 template <typename OT, int NW>
@@ -551,15 +569,19 @@ __device__ __forceinline__ void stage_fetch(const Img& im, int x0, int row0, int
   }
 }
 
-// Builds this thread's item of one 16-row block of G channels (frequency
-// k) into LDS from the values stage_fetch loaded.  Element (row, col) of
-// channel g, word part h sits at buf[((h * STAGE_CH + g) * 16 + row) * PC +
-// col], col 0 = column x0 - r.  `interior`: the block's items lie inside
-// the image (no masks).
-template <typename OT, int G, int IW, bool INTERIOR>
-__device__ __forceinline__ void stage_block(const Img& im, float kinv, float shift, int x0,
+// Builds this thread's item of one 16-row block of a group of G channels
+// (frequencies k, k+1, .. as group_freqs; f first when group_has_f) into
+// LDS from the values stage_fetch loaded.  Element (row, col) of channel g,
+// word part h sits at buf[((h * SCH + g) * 16 + row) * PC + col], col 0 =
+// column x0 - r.  `interior`: the block's items lie inside the image (no
+// masks).
+template <typename OT, int G, int IW, bool INTERIOR, int SCH = STAGE_CH>
+__device__ __forceinline__ void stage_block(const Img& im, int k, float shift, int x0,
                                            int row0, int CWn, int PC, typename Stage<OT>::T* buf,
                                            const float (&fvs)[IW]) {
+  constexpr bool HF = group_has_f<G>();
+  constexpr int NF = group_freqs<G>();
+  static_assert(G == (HF ? 1 : 0) + 4 * NF && G <= SCH, "bad channel group");
   using S = Stage<OT>;
   constexpr int NP = S::kParts;
   const int per_row = (CWn + IW - 1) / IW;
@@ -570,35 +592,45 @@ __device__ __forceinline__ void stage_block(const Img& im, float kinv, float shi
   const int row = row0 + rr;
   const int col0 = x0 - im.r + c0;
   const bool rin = static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
-  float x[G][IW];
+  bool in[IW];
+  float fs[IW];
 #pragma unroll
   for (int j = 0; j < IW; ++j) {
-    const bool in =
-        INTERIOR || (rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W));
-    const float f = in ? fvs[j] : 0.f;
-    const float fs = in ? fvs[j] - shift : 0.f;     // f - m, zero outside
-    if (G == 1) {
-      x[0][j] = fs;
-    } else {
-      float sn, cs;
-      sincos_rev(kinv * f, &sn, &cs);
-      x[0][j] = cs * fs;
-      x[1][j] = sn * fs;
-      x[2][j] = in ? cs : 0.f;
-      x[3][j] = in ? sn : 0.f;
-    }
+    in[j] = INTERIOR || (rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W));
+    fs[j] = in[j] ? fvs[j] - shift : 0.f;     // f - m, zero outside
   }
   // IW is even and c0 a multiple of IW: pairs of words are 4-byte aligned
-#pragma unroll
-  for (int g = 0; g < G; ++g)
+  auto put = [&](int g, const float (&x)[IW]) {
 #pragma unroll
     for (int j = 0; j < IW / 2; ++j) {
       uint32_t w[NP];
-      S::pack2(x[g][2 * j], x[g][2 * j + 1], w);
+      S::pack2(x[2 * j], x[2 * j + 1], w);
 #pragma unroll
       for (int h = 0; h < NP; ++h)
-        reinterpret_cast<uint32_t*>(buf + ((h * STAGE_CH + g) * 16 + rr) * PC + c0)[j] = w[h];
+        reinterpret_cast<uint32_t*>(buf + ((h * SCH + g) * 16 + rr) * PC + c0)[j] = w[h];
     }
+  };
+  if (HF) put(0, fs);
+  // one frequency at a time: its four channels are written before the
+  // next frequency's trig, which bounds the registers a group needs
+#pragma unroll
+  for (int q = 0; q < NF; ++q) {
+    constexpr int g0 = HF ? 1 : 0;
+    const float kinv = static_cast<float>(k + q) * im.inv_period;
+    float x[4][IW];
+#pragma unroll
+    for (int j = 0; j < IW; ++j) {
+      const float f = in[j] ? fvs[j] : 0.f;
+      float sn, cs;
+      sincos_rev(kinv * f, &sn, &cs);
+      x[0][j] = cs * fs[j];
+      x[1][j] = sn * fs[j];
+      x[2][j] = in[j] ? cs : 0.f;
+      x[3][j] = in[j] ? sn : 0.f;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) put(g0 + 4 * q + c, x[c]);
+  }
 }
 
 // =========================================================================
@@ -822,6 +854,17 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   using S = Stage<OT>;
   typedef typename S::v8 v8;
   typedef typename S::T o4 __attribute__((ext_vector_type(4)));
+  constexpr bool HF = group_has_f<G>();      // channel f leads the group
+  constexpr int NF = group_freqs<G>();       // frequencies k .. k+NF-1
+  constexpr int SCH = staged_channels<OT, GND>();
+  static_assert(G == (HF ? 1 : 0) + 4 * NF && G <= SCH, "bad channel group");
+  // sub-groups: {f} when present, then one per frequency (4 channels)
+  constexpr int NSG = (HF ? 1 : 0) + NF;
+  // the merged groups run sub-group by sub-group (fewer accumulators live
+  // at once); one-frequency groups keep their all-channels-at-once order
+  constexpr bool SUB = staged_merge<OT, GND>();
+  auto sg_first = [](int sg) { return HF ? (sg == 0 ? 0 : 4 * sg - 3) : 4 * sg; };
+  auto sg_size = [](int sg) { return (HF && sg == 0) ? 1 : 4; };
   constexpr int SHS = (DV + 1) / 2;          // 32-column horizontal steps
   constexpr int NV = (DV + 1) / 2;           // vertical MFMAs (2 blocks each)
   constexpr int PC = stage_pitch(stage_width<DV, NW>());
@@ -832,8 +875,13 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const float kinv = static_cast<float>(k) * im.inv_period;
-  const float ck = cS[k];
+  float kinv[NF > 0 ? NF : 1], ck[NF > 0 ? NF : 1];
+#pragma unroll
+  for (int q = 0; q < NF; ++q) {
+    kinv[q] = static_cast<float>(k + q) * im.inv_period;
+    ck[q] = cS[k + q];
+  }
+  const float c0 = cS[0];
   const int x0w = x0 + wave * MSTRIP;
   const int QB = nblk + DV - 1;
   constexpr int IW = stage_item_width<DV, NW>();
@@ -910,7 +958,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
       const int q = qq + u;
       if (q < QB) {
         constexpr int NBUF = staged_bufs<OT, NW, GND>();
-        typename S::T* buf = sbuf + (NBUF == 2 ? (q & 1) : 0) * (NS * STAGE_CH * 16 * PC);
+        typename S::T* buf = sbuf + (NBUF == 2 ? (q & 1) : 0) * (NS * SCH * 16 * PC);
         const int row0 = y0 - r + 16 * q;
         const int pb = q - (DV - 1);
         // output-pixel values for this block's fold, loaded before the
@@ -922,10 +970,10 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             nv[v] = Ns[pb * 256 + 64 * v + lane];
-            if (G == 4) dv[v] = Ds[pb * 256 + 64 * v + lane];
+            if (NF > 0) dv[v] = Ds[pb * 256 + 64 * v + lane];
           }
         }
-        if (G == 4) {
+        if (NF > 0) {
           const int gx = min(x0w + li, im.W - 1);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -934,13 +982,14 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
           }
         }
         if (block_interior(row0))
-          stage_block<OT, G, IW, true>(im, kinv, shift, x0, row0, CWn, PC, buf, fvs);
+          stage_block<OT, G, IW, true, SCH>(im, k, shift, x0, row0, CWn, PC, buf, fvs);
         else
-          stage_block<OT, G, IW, false>(im, kinv, shift, x0, row0, CWn, PC, buf, fvs);
+          stage_block<OT, G, IW, false, SCH>(im, k, shift, x0, row0, CWn, PC, buf, fvs);
         // next block's loads (the last block reloads its own: branch-free)
         const int rown = y0 - r + 16 * ((q + 1 < QB) ? q + 1 : q);
         stage_fetch<IW>(im, x0, rown, CWn, block_interior(rown), fvs);
         __syncthreads();
+        if constexpr (!SUB) {
         // ---- horizontal pass of this wave's strip ----
         f4 acc[G];
 #pragma unroll
@@ -952,7 +1001,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
             v8 a[NS];
 #pragma unroll
             for (int h = 0; h < NS; ++h)
-              a[h] = *reinterpret_cast<const v8*>(buf + ((h * STAGE_CH + g) * 16 + li) * PC +
+              a[h] = *reinterpret_cast<const v8*>(buf + ((h * SCH + g) * 16 + li) * PC +
                                                   16 * wave + 32 * s + 8 * lk);
             // hi*hi (+ lo*hi + hi*lo when values are split)
 #pragma unroll
@@ -1023,25 +1072,147 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               nv[v] = nrow[64 * v];
-              if (G == 4) dv[v] = drow[64 * v];
+              if (NF > 0) dv[v] = drow[64 * v];
             }
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            if (G == 1) {
-              nv[v] = fmaf(ck, vacc[0][v], nv[v]);
+            if (HF) {
+              nv[v] = fmaf(c0, vacc[0][v], nv[v]);
             } else {
               float sn, cs;
-              sincos_rev(kinv * fo[v], &sn, &cs);
-              nv[v] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), nv[v]);
-              dv[v] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), dv[v]);
+              sincos_rev(kinv[0] * fo[v], &sn, &cs);
+              nv[v] = fmaf(ck[0], fmaf(cs, vacc[0][v], sn * vacc[1][v]), nv[v]);
+              dv[v] = fmaf(ck[0], fmaf(cs, vacc[2][v], sn * vacc[3][v]), dv[v]);
             }
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             nrow[64 * v] = nv[v];
-            if (G == 4) drow[64 * v] = dv[v];
+            if (NF > 0) drow[64 * v] = dv[v];
           }
+        }
+        } else {
+        // ---- horizontal pass of this wave's strip, one sub-group (f, or
+        // one frequency's four channels) at a time, each converted into the
+        // ring right away (fewer accumulators live at once) ----
+#pragma unroll
+        for (int sg = 0; sg < NSG; ++sg) {
+          const int gb = sg_first(sg), gn = sg_size(sg);
+          f4 acc[4];
+#pragma unroll
+          for (int i = 0; i < gn; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < SHS; ++s)
+#pragma unroll
+            for (int i = 0; i < gn; ++i) {
+              v8 a[NS];
+#pragma unroll
+              for (int h = 0; h < NS; ++h)
+                a[h] = *reinterpret_cast<const v8*>(buf + ((h * SCH + gb + i) * 16 + li) * PC +
+                                                    16 * wave + 32 * s + 8 * lk);
+              // hi*hi (+ lo*hi + hi*lo when values are split)
+#pragma unroll
+              for (int ha = 0; ha < NS; ++ha)
+#pragma unroll
+                for (int hb = 0; hb + ha < NS; ++hb) acc[i] = S::mfma(a[ha], Bw[s][hb], acc[i]);
+            }
+#pragma unroll
+          for (int i = 0; i < gn; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              ring[u][0][gb + i][v] = S::cvt(acc[i][v]);
+              if (NS == 2)
+                ring[u][NS - 1][gb + i][v] =
+                    S::cvt(acc[i][v] - static_cast<float>(ring[u][0][gb + i][v]));
+            }
+        }
+        // one buffer: every wave is done reading it before the next block
+        // is staged into it
+        if (NBUF == 1) __syncthreads();
+
+        // ---- vertical pass, output block pb = q - DV + 1, and the fold,
+        // sub-group by sub-group ----
+        if (pb >= 0) {
+          // fold (all reads of N, D before the writes they may alias)
+          float* const nrow = Ns + pb * 256 + lane;
+          float* const drow = Ds + pb * 256 + lane;
+          if (!GND) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              nv[v] = nrow[64 * v];
+              if (NF > 0) dv[v] = drow[64 * v];
+            }
+          }
+#pragma unroll
+          for (int sg = 0; sg < NSG; ++sg) {
+            const int gb = sg_first(sg), gn = sg_size(sg);
+            f4 vacc[4];
+#pragma unroll
+            for (int i = 0; i < gn; ++i) vacc[i] = f4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (GND) {
+#pragma unroll
+              for (int d = 0; d < DV; ++d) {
+                const int slot = (u + 1 + d) % DV;
+                o4 aw[NS];
+#pragma unroll
+                for (int h = 0; h < NS; ++h)
+                  aw[h] = kVtapLds ? vtap4[(d * NS + h) * 64 + lane] : Aw4[d][h];
+#pragma unroll
+                for (int i = 0; i < gn; ++i)
+#pragma unroll
+                  for (int ha = 0; ha < NS; ++ha)
+#pragma unroll
+                    for (int hb = 0; hb + ha < NS; ++hb)
+                      vacc[i] = S::mfma16(aw[ha], ring[slot][hb][gb + i], vacc[i]);
+              }
+            } else {
+#pragma unroll
+              for (int t = 0; t < NV; ++t) {
+                const int b0 = 2 * t, b1 = (2 * t + 1 < DV) ? 2 * t + 1 : 2 * t;
+                v8 aw[NS];
+#pragma unroll
+                for (int h = 0; h < NS; ++h)
+                  aw[h] = kVtapLds ? vtap[(t * NS + h) * 64 + lane] : Aw[t][h];
+#pragma unroll
+                for (int i = 0; i < gn; ++i) {
+                  v8 b[NS];
+#pragma unroll
+                  for (int h = 0; h < NS; ++h) {
+                    const o4 e0 = ring[(u + 1 + b0) % DV][h][gb + i];
+                    const o4 e1 = ring[(u + 1 + b1) % DV][h][gb + i];
+                    b[h] = v8{e0[0], e0[1], e0[2], e0[3], e1[0], e1[1], e1[2], e1[3]};
+                  }
+#pragma unroll
+                  for (int ha = 0; ha < NS; ++ha)
+#pragma unroll
+                    for (int hb = 0; hb + ha < NS; ++hb)
+                      vacc[i] = S::mfma(aw[ha], b[hb], vacc[i]);
+                }
+              }
+            }
+            // f first, then the frequencies in order: the additions into
+            // N and D are those of one group per frequency
+            if (HF && sg == 0) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) nv[v] = fmaf(c0, vacc[0][v], nv[v]);
+            } else {
+              const int qf = max(0, HF ? sg - 1 : sg);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                float sn, cs;
+                sincos_rev(kinv[qf] * fo[v], &sn, &cs);
+                nv[v] = fmaf(ck[qf], fmaf(cs, vacc[0][v], sn * vacc[1][v]), nv[v]);
+                dv[v] = fmaf(ck[qf], fmaf(cs, vacc[2][v], sn * vacc[3][v]), dv[v]);
+              }
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            nrow[64 * v] = nv[v];
+            if (NF > 0) drow[64 * v] = dv[v];
+          }
+        }
         }
       }
     }
@@ -1075,9 +1246,23 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
   const float shift = im.in[static_cast<size_t>(min(y0 + TYo / 2, im.H - 1)) * im.ld_in +
                             min(x0 + NW * MSTRIP / 2, im.W - 1)];
   init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);
-  staged_group<OT, DV, 1, NW, GND>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
-  for (int k = 1; k < im.K; ++k)
-    staged_group<OT, DV, 4, NW, GND>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+  if constexpr (staged_merge<OT, GND>()) {
+    // {f, 1}, {2, 3}, {4, 5}, .. (and a last single frequency for even K)
+    if (im.K == 1) {
+      staged_group<OT, DV, 1, NW, GND>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+    } else {
+      staged_group<OT, DV, 5, NW, GND>(im, 1, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+      int k = 2;
+      for (; k + 1 < im.K; k += 2)
+        staged_group<OT, DV, 8, NW, GND>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+      if (k < im.K)
+        staged_group<OT, DV, 4, NW, GND>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+    }
+  } else {
+    staged_group<OT, DV, 1, NW, GND>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+    for (int k = 1; k < im.K; ++k)
+      staged_group<OT, DV, 4, NW, GND>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+  }
   store_nd(im, x0w, y0, nblk, Ns, Ds, lane, shift);
 }
 

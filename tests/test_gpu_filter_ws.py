@@ -92,8 +92,6 @@ def test_ws_shapes_against_oracle_and_lds_form(prec, H, W, theta, K, sigma, pad)
     f = workloads.voronoi_image(H, W, max(4, H * W // 65536), True, H + 7 * W)
     T, c = fitted(sigma, K)
     got, used = run_ws(f, theta, K, T, c, prec, pad=pad)
-    # every precision gets a workspace at these sizes (single-word fp16 at
-    # DV < 5 is sized for the two-word mode it may run as, and ignores it)
     assert used
     ys, xs = points(H, W, 300, H * 3 + W)
     ref, num, den = O.brute_bf_points(f, theta, O.cosine_series(c, T), ys, xs)
@@ -112,14 +110,13 @@ def test_ws_shapes_against_oracle_and_lds_form(prec, H, W, theta, K, sigma, pad)
 
 def test_ws_falls_back_where_not_used():
     """Short or narrow images and the largest radius class need no
-    workspace, and single-word fp16 at small radii does not use the one it
-    is sized for: fobf_filter_ws then equals fobf_filter bit for bit."""
+    workspace: fobf_filter_ws then equals fobf_filter bit for bit."""
     import torch
     import paper_1811_02168_amd as F
-    cases = [(4096, 512, 10.0, "fp32"), (2048, 2048, 5.0, "fp16"),
+    cases = [(4096, 512, 10.0, "fp32"), (1024, 2048, 5.0, "fp16"),
              (600, 700, 5.0, "fp16x2"), (2048, 2048, 15.0, "bf16")]
     for H, W, theta, prec in cases:
-        assert (F.filter_workspace_size(H, W, theta, prec) == 0) == (prec != "fp16")
+        assert F.filter_workspace_size(H, W, theta, prec) == 0
         f = workloads.voronoi_image(H, W, 64, True, 31 + H)
         T, c = fitted(40.0, 6)
         img = torch.from_numpy(f.astype(np.float32)).cuda()
@@ -217,3 +214,27 @@ def test_ws_fp32_bitwise_random():
         print("fp32 ws bitwise", case, H, W, round(theta, 2), K, ws_used)
         assert np.array_equal(got, ref.cpu().numpy().astype(np.float64)), (case, H, W, theta)
     assert used >= 12
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 7])
+def test_ws_fp16_every_group_shape(K):
+    """The fp16 workspace form folds channel groups two frequencies at a
+    time ({f, 1}, {2, 3}, .., a last single frequency when K is even, {f}
+    alone when K = 1).  Every one of those shapes on a 2048^2 image at
+    theta = 10 against eq. (1) with the same cosine series at sampled
+    pixels.  The series is the normalised Fejer kernel (non-negative, so
+    single-word fp16 staging is kept: fobf_effective_prec)."""
+    import paper_1811_02168_amd as F
+    H = W = 2048
+    theta, T = 10.0, 200
+    c = np.array([1.0 / K] + [2.0 * (1.0 - k / K) / K for k in range(1, K)])
+    assert F.effective_prec("fp16", K, T, c) == F.FP16_STAGE
+    f = workloads.voronoi_image(H, W, 64, True, 77 + K)
+    got, used = run_ws(f, theta, K, T, c, "fp16")
+    assert used
+    ys, xs = points(H, W, 300, 5 + K)
+    ref, num, den = O.brute_bf_points(f, theta, O.cosine_series(c, T), ys, xs)
+    mask = den / O.blur_weight(H, W, theta)[ys, xs] >= 0.01
+    err = float(np.max(np.abs(got[ys, xs] - ref)[mask]))
+    print("ws fp16 groups K", K, err)
+    assert err <= TOL["fp16"]

@@ -129,8 +129,6 @@ def test_filter_workspace_without_device():
     import ctypes as C
     import paper_1811_02168_amd as F
     size = F.filter_workspace_size
-    # single fp16 uses the workspace form at DV >= 5 only, but a call may
-    # run as two-word fp16 (a series with negative lobes): sized for that
     assert size(4096, 4096, 8.0, "fp16") == size(4096, 4096, 8.0, "fp16x2") > 0
     assert size(4096, 4096, 10.0, "fp16") == 8 * 4096 * 4096
     for prec in ("fp32", "bf16", "fp16x2"):
@@ -336,3 +334,4 @@ def test_effective_prec_reroutes_series_with_negative_lobes():
     assert F.lib.fobf_effective_prec(1, 0, 40, arr) == -1
     assert F.lib.fobf_effective_prec(1, 2, 0, arr) == -1
     assert F.lib.fobf_effective_prec(1, 2, 40, None) == -1
+

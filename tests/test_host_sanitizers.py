@@ -47,6 +47,10 @@ int main(int argc, char** argv) {
   bad += check(fobf_fit_samples(63, nullptr, 5, 1e9, 0, &c) == FOBF_EINVAL, "null b");
   bad += check(fobf_fit_period(255, 40.0, 4, 255, &c) == FOBF_OK && c.T == 255, "period");
   bad += check(fobf_fit_period(255, 40.0, 6, 2, &c) == FOBF_EINVAL, "period rank");
+  bad += check(fobf_fit_warm(255, 50.0, 4, 0.1, 0, 0, &c) == FOBF_OK && c.T == 203, "warm");
+  bad += check(fobf_fit_warm(255, 50.0, 8, 0.1, 0, 2000, &c) == FOBF_OK, "warm clamp");
+  bad += check(fobf_fit_warm(255, 50.0, 0, 0.1, 0, 0, &c) == FOBF_EINVAL, "warm K = 0");
+  bad += check(fobf_fit_warm(255, 50.0, 4, 0.1, 0, 0, nullptr) == FOBF_EINVAL, "warm null");
   bad += check(fobf_fit_cache_clear() >= 1, "cache clear");
   const double sig[3] = {20.0, 40.0, 80.0}, eps[2] = {1e-1, 1e-3};
   fobf_lut* lut = nullptr;
