@@ -466,9 +466,13 @@ struct Stage<F16Pair> {
   }
 };
 
-// LDS pitch (elements) of a staged channel row: >= cw, = 24 (mod 64) so
-// that the 16 rows read by one 16-lane group fall in distinct banks.
-__host__ __device__ constexpr int stage_pitch(int cw) { return ((cw + 39) / 64) * 64 + 24; }
+// LDS pitch (elements) of a staged channel row: >= cw, = 16 (mod 64).  Of
+// the residues 8, 16, 24, 40 and 56 (all keep the 16-byte reads aligned)
+// 16 is the fastest for every staged kernel at 4096^2, theta = 10 (3-4%
+// over 24).  The LDS bank-conflict counter does not depend on the residue
+// (equal counts at 8 and 24): it reads 4 cycles per 16-byte read, which
+// the width of the read sets, not the row layout.
+__host__ __device__ constexpr int stage_pitch(int cw) { return ((cw + 47) / 64) * 64 + 16; }
 // staged columns: the window of the last of NW strips ends at
 // 16 (NW - 1) + 32 SHS (columns past 16 NW + 2r only ever meet zero taps)
 __host__ __device__ constexpr int stage_cols(int shs, int nw) { return 16 * (nw - 1) + 32 * shs; }
