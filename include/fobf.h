@@ -44,7 +44,8 @@ typedef enum {
   FOBF_ENOMEM = -2,    /* allocation failed or request exceeds the budget   */
   FOBF_EHIP = -3,      /* a HIP runtime call failed                         */
   FOBF_EINTERNAL = -4, /* internal error                                    */
-  FOBF_ECANCELED = -5  /* serving: request cancelled or server stopped      */
+  FOBF_ECANCELED = -5, /* serving: request cancelled or server stopped      */
+  FOBF_ETIMEDOUT = -6  /* serving: not admitted before its deadline         */
 } fobf_status;
 
 typedef enum {
@@ -171,6 +172,18 @@ void fobf_lut_destroy(fobf_lut* lut);
  * affected.  Thread-safe; never fails.
  */
 int fobf_fit_cache_clear(void);
+
+/*
+ * fobf_fit_cache_save / fobf_fit_cache_load -- keep fobf_fit's cache across
+ * processes: save writes every cached (R, sigma, K, eps, Tmax) -> (T, c, E,
+ * delta) entry to a text file (doubles in hexadecimal, so a round trip is
+ * exact); load adds a file's entries to the cache (replacing equal keys),
+ * after which fobf_fit returns them without solving eq. (5) again.  A
+ * missing or malformed file gives FOBF_EINVAL and leaves the cache as it
+ * was.  Thread-safe.
+ */
+fobf_status fobf_fit_cache_save(const char* path);
+fobf_status fobf_fit_cache_load(const char* path);
 
 /*
  * fobf_fit_samples -- the same fit for an arbitrary even range kernel given
@@ -378,6 +391,8 @@ typedef struct {
   double theta, sigma;
   int K;                    /* order (>=1)                                 */
   int prec;                 /* fobf_prec                                   */
+  double deadline_s;        /* admit within this many seconds of submit,   */
+                            /* else FOBF_ETIMEDOUT (0 = no deadline, >= 0) */
 } fobf_request;
 
 typedef struct {
@@ -397,6 +412,13 @@ fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req,
  * gives FOBF_EINVAL.  Thread-safe. */
 fobf_status fobf_serve_poll(fobf_server* s, uint64_t ticket, int wait,
                             fobf_result* res);
+/* Cancels a request that is still queued (not yet admitted to the device):
+ * it completes at once with FOBF_ECANCELED (poll it to release the ticket)
+ * and returns FOBF_OK.  FOBF_EBUSY when the request is already on the device
+ * (it completes normally), FOBF_EINVAL for an unknown ticket or a request
+ * that has completed.  Cancelled and timed-out requests count as completed
+ * and failed in the statistics.  Thread-safe. */
+fobf_status fobf_serve_cancel(fobf_server* s, uint64_t ticket);
 /* Requests still queued when the server is destroyed complete with
  * FOBF_ECANCELED; work already on the device finishes first.  Tickets are
  * invalid afterwards.  No other call on the same server may be running

@@ -14,7 +14,9 @@
 // and E is evaluated from the explicit residual.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -402,6 +404,81 @@ extern "C" int fobf_fit_cache_clear(void) {
   const int n = static_cast<int>(g_cache.size());
   g_cache.clear();
   return n;
+}
+
+// Cache file: one line per entry, "key_K R Tmax sigma eps T K E delta c_0 ..
+// c_{K-1}", the doubles as C99 hexadecimal floats so that a round trip is
+// exact.
+extern "C" fobf_status fobf_fit_cache_save(const char* path) {
+  if (!path) return fail(FOBF_EINVAL, "fobf_fit_cache_save: path is NULL");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(FOBF_EINVAL, std::string("fobf_fit_cache_save: cannot open ") + path);
+  std::fprintf(f, "# fobf fit cache v1: keyK R Tmax sigma eps T K E delta c[0..K-1]\n");
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (const auto& kv : g_cache) {
+      double sigma, eps;
+      const uint64_t sb = std::get<1>(kv.first), eb = std::get<3>(kv.first);
+      std::memcpy(&sigma, &sb, sizeof(sigma));
+      std::memcpy(&eps, &eb, sizeof(eps));
+      const fobf_coef& c = kv.second;
+      std::fprintf(f, "%d %d %d %a %a %d %d %a %a", std::get<2>(kv.first), std::get<0>(kv.first),
+                   std::get<4>(kv.first), sigma, eps, c.T, c.K, c.E, c.delta);
+      for (int k = 0; k < c.K; ++k) std::fprintf(f, " %a", c.c[k]);
+      std::fprintf(f, "\n");
+    }
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok ? FOBF_OK : fail(FOBF_EINVAL, "fobf_fit_cache_save: write failed");
+}
+
+extern "C" fobf_status fobf_fit_cache_load(const char* path) {
+  if (!path) return fail(FOBF_EINVAL, "fobf_fit_cache_load: path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(FOBF_EINVAL, std::string("fobf_fit_cache_load: cannot open ") + path);
+  std::vector<std::pair<std::tuple<int, uint64_t, int, uint64_t, int>, fobf_coef>> rows;
+  char line[4096];
+  bool bad = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int keyK, R, Tmax, T, K, used = 0;
+    double sigma, eps, E, delta;
+    if (std::sscanf(line, "%d %d %d %la %la %d %d %la %la%n", &keyK, &R, &Tmax, &sigma, &eps, &T,
+                    &K, &E, &delta, &used) != 9) {
+      bad = true;
+      break;
+    }
+    if (R < 1 || K < 1 || K > FOBF_KMAX || keyK < 0 || keyK > FOBF_KMAX ||
+        (keyK != 0 && keyK != K) || T < 1 || Tmax < T || !(sigma > 0.0) || !(eps > 0.0) ||
+        !std::isfinite(E) || !std::isfinite(delta)) {
+      bad = true;
+      break;
+    }
+    fobf_coef c{};
+    c.R = R;
+    c.K = K;
+    c.T = T;
+    c.Tmax = Tmax;
+    c.sigma = sigma;
+    c.E = E;
+    c.delta = delta;
+    const char* p = line + used;
+    for (int k = 0; k < K; ++k) {
+      int n = 0;
+      if (std::sscanf(p, " %la%n", &c.c[k], &n) != 1 || !std::isfinite(c.c[k])) {
+        bad = true;
+        break;
+      }
+      p += n;
+    }
+    if (bad) break;
+    rows.push_back({std::make_tuple(R, bits(sigma), keyK, bits(eps), Tmax), c});
+  }
+  std::fclose(f);
+  if (bad) return fail(FOBF_EINVAL, "fobf_fit_cache_load: malformed line");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& r : rows) g_cache[r.first] = r.second;
+  return FOBF_OK;
 }
 
 extern "C" fobf_status fobf_fit_samples(int R, const double* b, int K,

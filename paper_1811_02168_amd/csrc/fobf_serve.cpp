@@ -420,6 +420,7 @@ void worker_main(fobf_server* s) {
   for (;;) {
     std::vector<Req*> adm;
     std::vector<Req*> cancelled;
+    std::vector<Req*> timed_out;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       // the first queued request whose fit has finished, if the limits let
@@ -434,7 +435,37 @@ void worker_main(fobf_server* s) {
         return s->pending.end();
       };
       auto admissible = [&]() { return next_ready() != s->pending.end(); };
-      s->cv_work.wait(lk, [&]() { return s->stop || admissible(); });
+      // queued requests past their admission deadline, and the earliest
+      // deadline still ahead (infinity when none)
+      auto deadline = [](const Req* q) {
+        return q->r.deadline_s > 0.0 ? q->res.t_submit + q->r.deadline_s : INFINITY;
+      };
+      auto expired_any = [&](double t) {
+        for (const Req* q : s->pending)
+          if (deadline(q) <= t) return true;
+        return false;
+      };
+      for (;;) {
+        if (s->stop || admissible() || expired_any(now_s())) break;
+        double next = INFINITY;
+        for (const Req* q : s->pending) next = std::min(next, deadline(q));
+        if (next == INFINITY) {
+          s->cv_work.wait(lk);
+        } else {
+          s->cv_work.wait_for(lk, std::chrono::duration<double>(std::max(0.0, next - now_s())));
+        }
+      }
+      {
+        const double t = now_s();
+        for (auto it = s->pending.begin(); it != s->pending.end();) {
+          if (deadline(*it) <= t) {
+            timed_out.push_back(*it);
+            it = s->pending.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      }
       if (s->stop) {
         while (!s->pending.empty()) {
           cancelled.push_back(s->pending.front());
@@ -455,7 +486,7 @@ void worker_main(fobf_server* s) {
         }
       }
     }
-    if (!cancelled.empty()) {
+    if (!cancelled.empty() || !timed_out.empty()) {
       const double t = now_s();
       {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -463,6 +494,13 @@ void worker_main(fobf_server* s) {
           q->res.status = FOBF_ECANCELED;
           q->res.t_done = t;
           q->done = true;
+        }
+        for (Req* q : timed_out) {
+          q->res.status = FOBF_ETIMEDOUT;
+          q->res.t_done = t;
+          q->done = true;
+          s->stats.completed += 1;
+          s->stats.failed += 1;
         }
       }
       s->cv_done.notify_all();
@@ -541,6 +579,8 @@ extern "C" fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad K");
   if (req->prec < FOBF_FP32 || req->prec > FOBF_FP16X2_STAGE)
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad precision");
+  if (!(req->deadline_s >= 0.0) || !std::isfinite(req->deadline_s))
+    return fail(FOBF_EINVAL, "fobf_serve_submit: bad deadline");
   const size_t bytes = request_bytes(req->H, req->W);
   if (bytes > s->cfg.hbm_budget_bytes)
     return fail(FOBF_ENOMEM, "fobf_serve_submit: request larger than the HBM budget");
@@ -592,6 +632,28 @@ extern "C" fobf_status fobf_serve_poll(fobf_server* s, uint64_t ticket, int wait
   delete q;
   if (st != FOBF_OK) set_error("fobf_serve_poll: request failed");
   return st;
+}
+
+extern "C" fobf_status fobf_serve_cancel(fobf_server* s, uint64_t ticket) {
+  if (!s) return fail(FOBF_EINVAL, "fobf_serve_cancel: NULL server");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end() || it->second->done)
+      return fail(FOBF_EINVAL, "fobf_serve_cancel: unknown or completed ticket");
+    Req* q = it->second;
+    auto pos = std::find(s->pending.begin(), s->pending.end(), q);
+    if (pos == s->pending.end()) return FOBF_EBUSY;   // on the device: completes normally
+    s->pending.erase(pos);
+    q->res.status = FOBF_ECANCELED;
+    q->res.t_done = now_s();
+    q->done = true;
+    s->stats.completed += 1;
+    s->stats.failed += 1;
+  }
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();   // the queue head may have changed
+  return FOBF_OK;
 }
 
 extern "C" fobf_status fobf_serve_inject_fault(fobf_server* s, int count) {

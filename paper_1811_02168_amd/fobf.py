@@ -23,7 +23,7 @@ FP32, FP16_STAGE, BF16_STAGE, FP16X2_STAGE = 0, 1, 2, 3
 ALGO_AUTO, ALGO_VALU, ALGO_MFMA = 0, 1, 2
 
 OK, WARN_TOL, EBUSY = 0, 1, 2
-EINVAL, ENOMEM, EHIP, EINTERNAL, ECANCELED = -1, -2, -3, -4, -5
+EINVAL, ENOMEM, EHIP, EINTERNAL, ECANCELED, ETIMEDOUT = -1, -2, -3, -4, -5, -6
 
 _PREC = {"fp32": FP32, "f32": FP32, "fp16": FP16_STAGE, "f16": FP16_STAGE,
          "bf16": BF16_STAGE, "fp16x2": FP16X2_STAGE}
@@ -38,7 +38,8 @@ EXPORTS = [
     "fobf_version", "fobf_peak", "fobf_fit_period", "fobf_lut_create", "fobf_lut_get",
     "fobf_lut_fit", "fobf_lut_save", "fobf_lut_load", "fobf_lut_destroy",
     "fobf_filter_workspace_size", "fobf_filter_ws", "fobf_effective_prec",
-    "fobf_filter_ws_static", "fobf_fit_warm",
+    "fobf_filter_ws_static", "fobf_fit_warm", "fobf_serve_cancel",
+    "fobf_fit_cache_save", "fobf_fit_cache_load",
 ]
 
 STATIC_SCRATCH_BYTES = 128 << 20     # FOBF_STATIC_SCRATCH_BYTES
@@ -72,7 +73,7 @@ class _Request(C.Structure):
     _fields_ = [("h_in", C.c_void_p), ("h_out", C.c_void_p), ("H", C.c_int),
                 ("W", C.c_int), ("ld_in", C.c_int), ("ld_out", C.c_int),
                 ("theta", C.c_double), ("sigma", C.c_double),
-                ("K", C.c_int), ("prec", C.c_int)]
+                ("K", C.c_int), ("prec", C.c_int), ("deadline_s", C.c_double)]
 
 
 class _ServeStats(C.Structure):
@@ -126,6 +127,7 @@ def _load():
     bind("fobf_serve_poll", [C.c_void_p, C.c_uint64, C.c_int,
                              C.POINTER(_Result)])
     bind("fobf_serve_destroy", [C.c_void_p])
+    bind("fobf_serve_cancel", [C.c_void_p, C.c_uint64])
     bind("fobf_serve_get_stats", [C.c_void_p, C.POINTER(_ServeStats)])
     bind("fobf_serve_inject_fault", [C.c_void_p, C.c_int])
     bind("fobf_autotune", [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p])
@@ -136,6 +138,8 @@ def _load():
                            C.POINTER(C.c_int)])
     bind("fobf_version", [])
     bind("fobf_fit_cache_clear", [])
+    bind("fobf_fit_cache_save", [C.c_char_p])
+    bind("fobf_fit_cache_load", [C.c_char_p])
     bind("fobf_peak", [C.c_int, C.c_void_p, C.POINTER(C.c_double)])
     bind("fobf_fit_period", [C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(_Coef)])
     bind("fobf_fit_warm", [C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int,
@@ -229,6 +233,16 @@ def fit_warm(R: int, sigma: float, K: int, eps: float = 0.1, T0: int = 0,
 def fit_cache_clear() -> int:
     """fobf_fit_cache_clear: drop the host fit cache; returns entries dropped."""
     return int(lib.fobf_fit_cache_clear())
+
+
+def fit_cache_save(path) -> None:
+    """fobf_fit_cache_save: write the host fit cache to a text file."""
+    _check(lib.fobf_fit_cache_save(str(path).encode()))
+
+
+def fit_cache_load(path) -> None:
+    """fobf_fit_cache_load: add a saved cache's entries to the fit cache."""
+    _check(lib.fobf_fit_cache_load(str(path).encode()))
 
 
 def fit_period(R: int, sigma: float, K: int, T: int) -> Coef:
@@ -487,10 +501,12 @@ class Server:
         self._keep = {}
 
     def submit(self, img: np.ndarray, out: np.ndarray, theta, sigma, K,
-               prec="fp32") -> int:
+               prec="fp32", deadline_s=0.0) -> int:
         """Queue one host image (2-D float32 with unit column stride; row
         pitch free).  Both arrays must stay alive and unchanged until the
-        ticket is polled done; pinned memory makes the copies async."""
+        ticket is polled done; pinned memory makes the copies async.
+        ``deadline_s`` > 0: the request completes with ETIMEDOUT if it is
+        not admitted to the device within that many seconds."""
         for a, nm in ((img, "img"), (out, "out")):
             if a.dtype != np.float32 or a.ndim != 2 or a.strides[1] != 4:
                 raise TypeError(f"{nm} must be 2-D float32 with unit column stride")
@@ -498,7 +514,7 @@ class Server:
             raise TypeError("out must have img's shape")
         req = _Request(img.ctypes.data, out.ctypes.data, img.shape[0],
                        img.shape[1], img.strides[0] // 4, out.strides[0] // 4,
-                       float(theta), float(sigma), int(K), _prec(prec))
+                       float(theta), float(sigma), int(K), _prec(prec), float(deadline_s))
         t = C.c_uint64()
         _check(lib.fobf_serve_submit(self._h, C.byref(req), C.byref(t)))
         self._keep[t.value] = (img, out)
@@ -516,6 +532,13 @@ class Server:
         if st != EBUSY:
             self._keep.pop(ticket, None)
         return st, res
+
+    def cancel(self, ticket: int) -> int:
+        """fobf_serve_cancel: OK if the queued request was cancelled (poll
+        it to release the ticket), EBUSY if it is already on the device."""
+        if ticket not in self._keep:
+            raise FobfError(EINVAL, "unknown ticket")
+        return _check(lib.fobf_serve_cancel(self._h, C.c_uint64(ticket)), (OK, EBUSY))
 
     def stats(self):
         st = _ServeStats()

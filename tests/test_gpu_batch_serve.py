@@ -462,3 +462,49 @@ def test_batch_and_serve_run_crude_fp16_series_as_two_word():
             res.append((r.prec, got))
     assert [p for p, _ in res] == [F.FP16X2_STAGE, F.FP16_STAGE, F.FP32]
     assert np.array_equal(res[0][1], o[0])
+
+
+def test_serve_cancel_and_deadline():
+    """fobf_serve_cancel and the per-request admission deadline: with one
+    request in flight at a time, a request queued behind a 4096^2 one can be
+    cancelled (ECANCELED, never runs), a request whose deadline passes
+    before it is admitted completes with ETIMEDOUT, one with a generous
+    deadline completes normally, and a request already on the device cannot
+    be cancelled (EBUSY, or EINVAL once it has completed)."""
+    import paper_1811_02168_amd as F
+
+    def pinned(a):
+        import torch
+        t = torch.empty(a.shape, dtype=torch.float32, pin_memory=True).numpy()
+        t[:] = a
+        return t
+
+    big = pinned(workloads.C3.image())
+    big_out = pinned(np.zeros(big.shape))
+    small = workloads.C1.image()[:64, :80].astype(np.float32)
+    outs = [np.full(small.shape, -1.0, dtype=np.float32) for _ in range(3)]
+    with F.Server(hbm_budget_bytes=4 << 30, max_inflight=1, max_batch=1) as srv:
+        srv.poll(srv.submit(small, outs[2], 3.0, 40.0, 4), wait=True)   # fit the key
+        t_big = srv.submit(big, big_out, 10.0, 40.0, 4)
+        t_c = srv.submit(small, outs[0], 3.0, 40.0, 4)
+        t_late = srv.submit(small, outs[1], 3.0, 40.0, 4, deadline_s=1e-4)
+        t_ok = srv.submit(small, outs[2], 3.0, 40.0, 4, deadline_s=30.0)
+        assert srv.cancel(t_c) == F.fobf.OK
+        st_c, r_c = srv.poll(t_c, wait=True)
+        st_late, _ = srv.poll(t_late, wait=True)
+        st_ok, _ = srv.poll(t_ok, wait=True)
+        try:
+            busy = srv.cancel(t_big)
+        except F.FobfError as e:
+            busy = e.status
+        st_big, _ = srv.poll(t_big, wait=True)
+        stats = srv.stats()
+    assert st_c == F.fobf.ECANCELED and r_c.t_done >= r_c.t_submit
+    assert np.all(outs[0] == -1.0)                   # never ran
+    assert st_late == F.fobf.ETIMEDOUT and np.all(outs[1] == -1.0)
+    assert st_ok == 0 and st_big == 0
+    assert busy in (F.fobf.EBUSY, F.fobf.EINVAL)
+    assert stats["failed"] == 2 and stats["completed"] == stats["submitted"] == 5
+    coef = F.fit(255, 40.0, 4, eps=0.1)
+    ref = O.fourier_direct(small.astype(np.float64), 3.0, 4, coef.T, coef.c)
+    assert float(np.max(np.abs(outs[2] - ref))) <= 0.05

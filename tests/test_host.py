@@ -335,3 +335,37 @@ def test_effective_prec_reroutes_series_with_negative_lobes():
     assert F.lib.fobf_effective_prec(1, 2, 0, arr) == -1
     assert F.lib.fobf_effective_prec(1, 2, 40, None) == -1
 
+
+
+def test_fit_cache_save_load_roundtrip(tmp_path):
+    """fobf_fit_cache_save / _load: entries written as hexadecimal floats
+    come back exactly (fixed-order fits and an Algorithm 1 result), a loaded
+    cache answers fobf_fit without the scan, and a malformed or missing file
+    is rejected with the cache left as it was."""
+    import paper_1811_02168_amd as F
+    F.fit_cache_clear()
+    a = F.fit(255, 37.5, 6, eps=0.1)
+    b = F.fit(255, 50.0, 0, eps=1e-3)           # Algorithm 1 (K* = 5)
+    path = tmp_path / "fits.txt"
+    F.fit_cache_save(path)
+    assert F.fit_cache_clear() == 2
+    F.fit_cache_load(path)
+    a2, b2 = F.fit(255, 37.5, 6, eps=0.1), F.fit(255, 50.0, 0, eps=1e-3)
+    for x, y in ((a, a2), (b, b2)):
+        assert (x.K, x.T, x.E, x.delta) == (y.K, y.T, y.E, y.delta)
+        assert np.array_equal(x.c, y.c)
+    # a planted entry is served as loaded: proof that the cache answered
+    lines = path.read_text().splitlines()
+    planted = [ln for ln in lines if ln.startswith("6 255 ")][0].split()
+    planted[5] = "123"                            # T
+    (tmp_path / "planted.txt").write_text(" ".join(planted) + "\n")
+    F.fit_cache_clear()
+    F.fit_cache_load(tmp_path / "planted.txt")
+    assert F.fit(255, 37.5, 6, eps=0.1).T == 123
+    F.fit_cache_clear()
+    (tmp_path / "bad.txt").write_text("6 255 1020 0x1p+5\n")
+    with pytest.raises(F.FobfError):
+        F.fit_cache_load(tmp_path / "bad.txt")
+    with pytest.raises(F.FobfError):
+        F.fit_cache_load(tmp_path / "missing.txt")
+    assert F.fit_cache_clear() == 0

@@ -51,6 +51,12 @@ int main(int argc, char** argv) {
   bad += check(fobf_fit_warm(255, 50.0, 8, 0.1, 0, 2000, &c) == FOBF_OK, "warm clamp");
   bad += check(fobf_fit_warm(255, 50.0, 0, 0.1, 0, 0, &c) == FOBF_EINVAL, "warm K = 0");
   bad += check(fobf_fit_warm(255, 50.0, 4, 0.1, 0, 0, nullptr) == FOBF_EINVAL, "warm null");
+  {
+    const std::string cpath = std::string(argv[1]) + "/fits.txt";
+    bad += check(fobf_fit_cache_save(cpath.c_str()) == FOBF_OK, "cache save");
+    bad += check(fobf_fit_cache_load(cpath.c_str()) == FOBF_OK, "cache load");
+    bad += check(fobf_fit_cache_load("/nonexistent/x") == FOBF_EINVAL, "cache load missing");
+  }
   bad += check(fobf_fit_cache_clear() >= 1, "cache clear");
   const double sig[3] = {20.0, 40.0, 80.0}, eps[2] = {1e-1, 1e-3};
   fobf_lut* lut = nullptr;
