@@ -81,7 +81,7 @@ fobf_status launch_f32_ws_sh(const ImageParams& p, int nblk, float* work, void* 
   (void)once;
   const int PC = f32s_pitch(SH, kWsWaves, p.r, stage_item_width<DV, kWsWaves>());
   const size_t lds = sizeof(float) * (LDS_TABLE + 8 * DV * 64 +
-                                      2 * static_cast<size_t>(STAGE_CH) * 16 * PC);
+                                      2 * static_cast<size_t>(kF32Ch) * 16 * PC);
   if (lds > 160 * 1024) return fail(FOBF_EINTERNAL, "fobf_filter_ws: staging exceeds the LDS");
   dim3 grid(padded_blocks(p, nblk, kWsWaves));
   hipLaunchKernelGGL(mfma_f32_ws_kernel<SH>, grid, dim3(64 * kWsWaves), lds,

@@ -652,11 +652,21 @@ __host__ __device__ constexpr int f32s_pitch(int sh, int nw, int r, int iw) {
   return ((m - 2 + 31) / 32) * 32 + 2;
 }
 
-// This thread's item of one block: G channels of frequency k (float32, no
-// shift) into buf[(g * 16 + row) * PC + col], col 0 = column x0 - r.
+// Channels per staging buffer of the float32 workspace form: its first
+// pass takes f together with frequency 1 (five channels), so that the f
+// channel's products (one accumulator chain on its own) overlap four
+// others and N and D make one round trip fewer; the sums and the order of
+// the additions into N and D are those of separate passes.
+constexpr int kF32Ch = 5;
+
+// This thread's item of one block: a group of G channels (f alone, one
+// frequency k: C f, S f, C, S, or f then frequency k) (float32, no shift)
+// into buf[(g * 16 + row) * PC + col], col 0 = column x0 - r.
 template <int G, int IW, bool INTERIOR>
 __device__ __forceinline__ void f32s_stage(const Img& im, float kinv, int x0, int row0, int CWn,
                                            int PC, float* buf, const float (&fvs)[IW]) {
+  constexpr bool HF = group_has_f<G>();
+  constexpr int g0 = HF ? 1 : 0;
   const int per_row = (CWn + IW - 1) / IW;
   const int it = threadIdx.x;
   if (it >= 16 * per_row) return;
@@ -671,15 +681,14 @@ __device__ __forceinline__ void f32s_stage(const Img& im, float kinv, int x0, in
     const bool in =
         INTERIOR || (rin && static_cast<unsigned>(col0 + j) < static_cast<unsigned>(im.W));
     const float f = in ? fvs[j] : 0.f;
-    if (G == 1) {
-      x[0][j] = f;
-    } else {
+    if (HF) x[0][j] = f;
+    if (G >= 4) {
       float sn, cs;
       sincos_rev(kinv * f, &sn, &cs);
-      x[0][j] = cs * f;
-      x[1][j] = sn * f;
-      x[2][j] = in ? cs : 0.f;
-      x[3][j] = in ? sn : 0.f;
+      x[g0][j] = cs * f;
+      x[g0 + 1][j] = sn * f;
+      x[g0 + 2][j] = in ? cs : 0.f;
+      x[g0 + 3][j] = in ? sn : 0.f;
     }
   }
   // IW is even and c0 a multiple of it: pairs are 8-byte aligned
@@ -707,11 +716,16 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
                                            const float (&atr)[4 * ((SH + 3) / 4)]) {
   constexpr int DV = (SH + 3) / 4;
   constexpr int IW = stage_item_width<DV, NW>();
+  constexpr bool HF = group_has_f<G>();      // f first (c_0 into N)
+  constexpr bool HK = G >= 4;                // frequency k (channels from g0)
+  constexpr int g0 = HF ? 1 : 0;
+  static_assert(G == 1 || G == 4 || G == 5, "bad channel group");
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const float kinv = static_cast<float>(k) * im.inv_period;
   const float ck = tbl[64 + k];
+  const float c0 = tbl[64];
   const int r = im.r;
   const int CWn = 16 * NW + 2 * r;
   const int x0w = x0 + wave * MSTRIP;
@@ -730,7 +744,7 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
     for (int u = 0; u < DV; ++u) {
       const int q = qq + u;
       if (q < QB) {
-        float* buf = sbuf + (q & 1) * (STAGE_CH * 16 * PC);
+        float* buf = sbuf + (q & 1) * (kF32Ch * 16 * PC);
         const int row0 = y0 - r + 16 * q;
         const int pb = q - (DV - 1);
         float fo[4], nv[4], dv[4];
@@ -738,10 +752,10 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             nv[v] = Ns[pb * 256 + 64 * v + lane];
-            if (G == 4) dv[v] = Ds[pb * 256 + 64 * v + lane];
+            if (HK) dv[v] = Ds[pb * 256 + 64 * v + lane];
           }
         }
-        if (G == 4) {
+        if (HK) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
@@ -787,21 +801,22 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
                                                                0, 0, 0);
             }
           }
+          // f's term first, then frequency k's: the additions of two
+          // separate passes
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            if (G == 1) {
-              nv[v] = fmaf(ck, vacc[0][v], nv[v]);
-            } else {
+            if (HF) nv[v] = fmaf(c0, vacc[0][v], nv[v]);
+            if (HK) {
               float sn, cs;
               sincos_rev(kinv * fo[v], &sn, &cs);
-              nv[v] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), nv[v]);
-              dv[v] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), dv[v]);
+              nv[v] = fmaf(ck, fmaf(cs, vacc[g0][v], sn * vacc[g0 + 1][v]), nv[v]);
+              dv[v] = fmaf(ck, fmaf(cs, vacc[g0 + 2][v], sn * vacc[g0 + 3][v]), dv[v]);
             }
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             Ns[pb * 256 + 64 * v + lane] = nv[v];
-            if (G == 4) Ds[pb * 256 + 64 * v + lane] = dv[v];
+            if (HK) Ds[pb * 256 + 64 * v + lane] = dv[v];
           }
         }
       }
@@ -824,7 +839,7 @@ __device__ __forceinline__ void f32s_tile(const Img& im, int tx, int ty, int nbl
   // whose taps are zero, so they must hold finite values
   {
     float4* z = reinterpret_cast<float4*>(sbuf);
-    const int n16 = 2 * STAGE_CH * 16 * PC / 4;
+    const int n16 = 2 * kF32Ch * 16 * PC / 4;
     for (int i = threadIdx.x; i < n16; i += 64 * NW) z[i] = float4{0.f, 0.f, 0.f, 0.f};
   }
   init_nd(im, tbl, x0 + wave * MSTRIP, y0, nblk, Ns, Ds, lane);
@@ -837,9 +852,13 @@ __device__ __forceinline__ void f32s_tile(const Img& im, int tx, int ty, int nbl
 #pragma unroll
     for (int i = 0; i < 4 * DV; ++i) atr[i] = At[i * 64 + lane];
   }
-  f32s_group<SH, NW, 1, TREG>(im, 0, x0, y0, nblk, tbl, Bt, At, sbuf, PC, Ns, Ds, btr, atr);
-  for (int k = 1; k < im.K; ++k)
-    f32s_group<SH, NW, 4, TREG>(im, k, x0, y0, nblk, tbl, Bt, At, sbuf, PC, Ns, Ds, btr, atr);
+  if (im.K == 1) {
+    f32s_group<SH, NW, 1, TREG>(im, 0, x0, y0, nblk, tbl, Bt, At, sbuf, PC, Ns, Ds, btr, atr);
+  } else {
+    f32s_group<SH, NW, 5, TREG>(im, 1, x0, y0, nblk, tbl, Bt, At, sbuf, PC, Ns, Ds, btr, atr);
+    for (int k = 2; k < im.K; ++k)
+      f32s_group<SH, NW, 4, TREG>(im, k, x0, y0, nblk, tbl, Bt, At, sbuf, PC, Ns, Ds, btr, atr);
+  }
   store_nd(im, x0 + wave * MSTRIP, y0, nblk, Ns, Ds, lane);
 }
 
