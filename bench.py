@@ -58,6 +58,9 @@ def parse():
                     help="turn the FETCH_SIZE / WRITE_SIZE counter passes of "
                     "--profile-run under DIR (DIR/FETCH_SIZE/*.csv, "
                     "DIR/WRITE_SIZE/*.csv) into profiles/fobf_c3_hbm_traffic.json, then exit")
+    ap.add_argument("--write-sq-summary", nargs=2, metavar=("PASS1_DIR", "PASS2_DIR"),
+                    help="turn the two SQ counter passes of --profile-run (rocprofv3 "
+                    "--pmc output directories) into profiles/fobf_c3_sq_counters.md, then exit")
     ap.add_argument("--write-trace-summary", nargs=2, metavar=("STATS_CSV", "BENCH_JSON"),
                     help="turn a rocprofv3 --kernel-trace --stats summary of a "
                     "bench run (and that run's JSON line) into "
@@ -150,6 +153,65 @@ def write_trace_summary(stats_csv, bench_json):
         fh.write("\n".join(out))
 
 
+SQ_PASSES = (
+    "SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_INSTS_MFMA SQ_INSTS_LDS "
+    "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS GRBM_GUI_ACTIVE",
+    "SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_WAIT_INST_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_ANY "
+    "SQ_INSTS_SALU SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VMEM_RD",
+)
+
+
+def write_sq_summary(d1, d2):
+    """profiles/fobf_c3_sq_counters.md from the two SQ counter passes of
+    `bench.py --profile-run`: per kernel, the counter totals of its dispatch
+    and the ratios that read them."""
+    import csv
+    import glob
+
+    vals = {}
+    for d in (d1, d2):
+        files = glob.glob(os.path.join(d, "*counter_collection.csv"))
+        if not files:
+            raise SystemExit(f"no counter CSV under {d}")
+        for r in csv.DictReader(open(files[0])):
+            for key, subs in TRAFFIC_KERNELS.items():
+                if any(x in r["Kernel_Name"] for x in subs):
+                    e = vals.setdefault(key, {})
+                    e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    keys = [k for k in TRAFFIC_KERNELS if k in vals]
+    counters = " ".join(SQ_PASSES).split()
+    out = ["# SQ counters of the single-image kernels (4096², θ = 10, K = 8, σ = 50)", "",
+           "One launch of each kernel (the `--profile-run` leg of `bench.py`: the 4096² "
+           "image, σ = 50, K = 8, fitted T), two counter passes of rocprofv3 on one MI355X "
+           "(gfx950), from the repository root:", "", "```", "cd /tmp && export TMPDIR=/tmp"]
+    for i, cs in enumerate(SQ_PASSES, 1):
+        out.append(f"timeout -s KILL 120 rocprofv3 --pmc {cs} -d <out>/sq{i} -o p{i} "
+                   "--output-format csv -- python3 bench.py --profile-run")
+    out += ["python3 bench.py --write-sq-summary <out>/sq1 <out>/sq2", "```", "",
+            "Values are the counter totals of the dispatch as rocprofv3 reports them "
+            "(summed over the chip; cycle counters in the SQ's own units).", "",
+            "| counter | " + " | ".join(KERNEL_LABELS[k].split(" (")[0] for k in keys) + " |",
+            "|---|" + "---|" * len(keys)]
+    for c in counters:
+        out.append(f"| {c} | " + " | ".join(f"{vals[k].get(c, float('nan')):,.0f}"
+                                            for k in keys) + " |")
+
+    def ratio(num, den):
+        return [vals[k].get(num, 0.0) / vals[k][den] if vals[k].get(den) else float("nan")
+                for k in keys]
+    rows = [("wait / wave cycles", ratio("SQ_WAIT_ANY", "SQ_WAVE_CYCLES")),
+            ("waiting to issue / wave cycles", ratio("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES")),
+            ("VALU active / wave cycles", ratio("SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES")),
+            ("LDS bank conflict / LDS active", ratio("SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS")),
+            ("LDS bank conflict / LDS instructions", ratio("SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS")),
+            ("VALU insts / MFMA insts", ratio("SQ_INSTS_VALU", "SQ_INSTS_MFMA"))]
+    for name, v in rows:
+        out.append(f"| {name} | " + " | ".join(f"{x:.2f}" for x in v) + " |")
+    out += ["", f"Kernel source hash (bench.py `kernel_source_hash`): {kernel_source_hash()}.", ""]
+    with open(os.path.join(ROOT, "profiles", "fobf_c3_sq_counters.md"), "w") as fh:
+        fh.write("\n".join(out))
+
+
 def profile_run(modes):
     import numpy as np
     import torch
@@ -181,7 +243,8 @@ def kernel_source_hash():
     so that only code changes invalidate recorded counters."""
     import re
     h = hashlib.sha256()
-    for name in ("fobf_tiles.h", "fobf_mfma.hip", "fobf_mfma_ws.hip", "fobf_tune.hip"):
+    for name in ("fobf_tiles.h", "fobf_mfma.hip", "fobf_mfma_ws.hip", "fobf_tune.hip",
+                 "fobf_valu.hip"):
         with open(os.path.join(ROOT, "paper_1811_02168_amd", "csrc", name)) as fh:
             src = fh.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
@@ -296,6 +359,9 @@ def main():
         return
     if args.write_trace_summary:
         write_trace_summary(*args.write_trace_summary)
+        return
+    if args.write_sq_summary:
+        write_sq_summary(*args.write_sq_summary)
         return
     if args.profile_run:
         profile_run([m for m in args.modes.split(",") if m])

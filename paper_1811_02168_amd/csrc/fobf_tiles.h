@@ -469,9 +469,9 @@ struct Stage<F16Pair> {
 // LDS pitch (elements) of a staged channel row: >= cw, = 16 (mod 64).  Of
 // the residues 8, 16, 24, 40 and 56 (all keep the 16-byte reads aligned)
 // 16 is the fastest for every staged kernel at 4096^2, theta = 10 (3-4%
-// over 24).  The LDS bank-conflict counter does not depend on the residue
-// (equal counts at 8 and 24): it reads 4 cycles per 16-byte read, which
-// the width of the read sets, not the row layout.
+// over 24), and the only one that clears the LDS bank-conflict counter
+// (0 cycles; 8 and 24 read 1.4x the LDS instruction cycles in conflicts,
+// 4 per 16-byte read).
 __host__ __device__ constexpr int stage_pitch(int cw) { return ((cw + 47) / 64) * 64 + 16; }
 // staged columns: the window of the last of NW strips ends at
 // 16 (NW - 1) + 32 SHS (columns past 16 NW + 2r only ever meet zero taps)
