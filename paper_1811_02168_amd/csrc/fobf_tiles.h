@@ -65,6 +65,18 @@ __device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
   *c = __builtin_amdgcn_cosf(t);
 }
 
+// An LDS pointer held in one register as it stands: the compiler may not
+// split it into a variable part plus a constant (which, when the constant
+// exceeds the 1 KB reach of the ds_read2 offset fields, costs one vector
+// add per read); the reads through it then take their small constant
+// offsets in the instruction's offset fields.
+template <typename T>
+__device__ __forceinline__ const T* lds_pinned(const T* p) {
+  auto q = (__attribute__((address_space(3))) const T*)p;
+  asm("" : "+v"(q));
+  return (const T*)q;
+}
+
 __device__ __forceinline__ float tap(const float* gS, int d, int r) {
   return (d >= -r && d <= r) ? gS[d < 0 ? -d : d] : 0.f;
 }
@@ -771,6 +783,14 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
         __syncthreads();
         // ---- horizontal pass of this wave's strip, from LDS ----
         const float* arow = buf + li * PC + 16 * wave + SH * lk;
+        // Pinned row pointers halve the kernel's vector adds; measured at
+        // 4096^2 they gain 0.8-1.9% where SH is not a multiple of 4 (theta
+        // = 6, 7, 10, 12) and lose 0.5-0.8% where it is (theta = 8, 5).
+        constexpr bool PIN = SH % 4 != 0;
+        const float* ag[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          ag[g] = PIN ? lds_pinned(arow + g * 16 * PC) : arow + g * 16 * PC;
         f4 acc[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
@@ -779,8 +799,7 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
           const float bh = TREG ? btr[s] : Bt[s * 64 + lane];
 #pragma unroll
           for (int g = 0; g < G; ++g)
-            acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[g * 16 * PC + s], bh, acc[g], 0,
-                                                          0, 0);
+            acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(ag[g][s], bh, acc[g], 0, 0, 0);
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) ring[u][g] = acc[g];
