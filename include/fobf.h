@@ -437,6 +437,43 @@ fobf_status fobf_serve_get_stats(fobf_server* s, fobf_serve_stats* out);
  * HIP error without launching anything (fault injection from the host). */
 fobf_status fobf_serve_inject_fault(fobf_server* s, int count);
 
+/* ---- debug-check build ------------------------------------------------
+ * libfobf_check.so is the same library compiled with FOBF_CHECKS=1: every
+ * kernel first fills its LDS allocation with all-ones words (NaN in
+ * float32, fp16 and bf16), so a read of LDS the kernel never wrote reaches
+ * the output as NaN, and checks its indices while it runs, recording each
+ * kind of violation as a bit in one device word instead of trapping:
+ *   FOBF_CHECK_LDS     LDS access outside the launch's dynamic allocation
+ *   FOBF_CHECK_IMAGE   image read outside the image (unclamped paths)
+ *   FOBF_CHECK_HALO_H  horizontal pass: a non-zero tap on a column outside
+ *                      the output column's window, or outside the staged
+ *                      columns of the block
+ *   FOBF_CHECK_HALO_V  vertical pass: a non-zero tap on a row outside the
+ *                      output row's window
+ *   FOBF_CHECK_RING    vertical pass: a ring slot holding another block
+ *                      than the one its taps are for
+ *   FOBF_CHECK_WS      workspace access outside the caller's workspace
+ *   FOBF_CHECK_OUT     output write outside the image or its pitch
+ *   FOBF_CHECK_TILE    batch: a tile index outside its job
+ *   FOBF_CHECK_STAGE   staging item outside its block row
+ * The release library computes the same outputs (the checks only read). */
+#define FOBF_CHECK_LDS 0x001u
+#define FOBF_CHECK_IMAGE 0x002u
+#define FOBF_CHECK_HALO_H 0x004u
+#define FOBF_CHECK_HALO_V 0x008u
+#define FOBF_CHECK_RING 0x010u
+#define FOBF_CHECK_WS 0x020u
+#define FOBF_CHECK_OUT 0x040u
+#define FOBF_CHECK_TILE 0x080u
+#define FOBF_CHECK_STAGE 0x100u
+
+/* Waits for the device to finish all work, then returns in *bits the
+ * violations recorded on the current device since the last call and
+ * clears them.  FOBF_EINVAL from the release library (built without
+ * checks) or when bits is NULL; FOBF_EHIP when the device cannot be read.
+ * For tests and debugging: it synchronises the whole device. */
+fobf_status fobf_check_take(unsigned int* bits);
+
 /* Thread-local message for the last non-OK status of this thread. */
 const char* fobf_last_error(void);
 

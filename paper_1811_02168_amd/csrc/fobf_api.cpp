@@ -42,6 +42,7 @@ void make_params(ImageParams& p, const float* in, float* out, int H, int W,
   p.r = spatial_radius(theta);
   p.K = K;
   p.inv_period = static_cast<float>(1.0 / (2.0 * T + 1.0));
+  p.check = check_word();
   for (int k = 0; k < K; ++k) p.c[k] = static_cast<float>(c[k]);
   const int r = p.r;
   double acc = 0.0;

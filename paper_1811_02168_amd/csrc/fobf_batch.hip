@@ -68,6 +68,7 @@ __global__ __launch_bounds__(MTHREADS, batch_min_blocks<DVHI>()) void batch_kern
   __shared__ int s_tile;
   float* tbl = lds;
   int cur = -1;
+  if (njobs > 0) poison_lds(FOBF_IMG(jobs[0].p));
   for (;;) {
     if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
     __syncthreads();
@@ -84,13 +85,16 @@ __global__ __launch_bounds__(MTHREADS, batch_min_blocks<DVHI>()) void batch_kern
     const int tx = lt - ty * J->ntx;
     const int nblk = J->nblk;
     const int dv = J->dv;
+    const Img im = FOBF_IMG(J->p);
+    FOBF_CHK(im, lt >= 0 && ty < J->nty && dv >= DVLO && dv <= DVHI, FOBF_CHECK_TILE);
+    // check builds: what the previous tile left in the LDS is poisoned
+    // again (the tables stay while the job does)
+    poison_lds(im, sizeof(float) * LDS_TABLE);
     if (lo != cur) {
       FOBF_LOAD_TABLES(J->p, tbl);
       cur = lo;
     }
     __syncthreads();
-    const Img im{J->p.in, J->p.out, J->p.H, J->p.W, J->p.ld_in, J->p.ld_out,
-                 J->p.r, J->p.K, J->p.inv_period};
     if constexpr (PREC == FOBF_FP32) {
       float* Bt = lds + LDS_TABLE;
       float* At = Bt + 4 * DVHI * 64;
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(MTHREADS, batch_min_blocks<DVHI>()) void batch_kern
 #define FOBF_F32_CASE(D)                                              \
   case D:                                                             \
     if constexpr (D >= DVLO && D <= DVHI) {                           \
-      build_f32_tables<4 * D>(tbl, im.r, Bt, At);                     \
+      build_f32_tables<4 * D>(im, tbl, im.r, Bt, At);                 \
       __syncthreads();                                                \
       f32_tile<4 * D>(im, tx, ty, nblk, tbl, Bt, At, nd);             \
     }                                                                 \
@@ -161,6 +165,25 @@ template <int PREC, int DVHI>
 size_t batch_lds_bytes() {
   return batch_fixed_lds<PREC, DVHI>() +
          sizeof(float) * MWAVES * 2 * batch_nblk_cap<PREC, DVHI>() * 256;
+}
+
+// dynamic LDS bytes of a launch class (precision, radius class)
+template <int PREC>
+size_t class_lds_bytes_p(int cidx) {
+  switch (cidx) {
+    case 0: return batch_lds_bytes<PREC, 4>();
+    case 1: return batch_lds_bytes<PREC, 5>();
+    default: return batch_lds_bytes<PREC, 7>();
+  }
+}
+
+size_t class_lds_bytes(int prec, int cidx) {
+  switch (prec) {
+    case FOBF_FP32: return class_lds_bytes_p<FOBF_FP32>(cidx);
+    case FOBF_FP16_STAGE: return class_lds_bytes_p<FOBF_FP16_STAGE>(cidx);
+    case FOBF_BF16_STAGE: return class_lds_bytes_p<FOBF_BF16_STAGE>(cidx);
+    default: return class_lds_bytes_p<FOBF_FP16X2_STAGE>(cidx);
+  }
 }
 
 template <int PREC, int DVLO, int DVHI>
@@ -300,6 +323,8 @@ fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t 
     while (k < es.size() && es[k].cls == es[i].cls) {
       table[k] = es[k].b;
       table[k].tile_begin = tiles;
+      table[k].p.lds_bytes = static_cast<int>(
+          class_lds_bytes(es[i].cls / kRadiusClasses, es[i].cls % kRadiusClasses));
       tiles += es[k].b.ntx * es[k].b.nty;
       ++k;
     }

@@ -30,12 +30,21 @@ struct ImageParams {
   int r;             // spatial radius
   int K;             // order
   float inv_period;  // 1 / (2T + 1)
-  int pad_;
+  int lds_bytes;     // dynamic LDS bytes of the launch (debug-check builds)
   const float* c_dev;       // when set: c_k read from this device array
   float c[FOBF_KMAX];       // c_k in float32
   float g[FOBF_RMAX + 1];   // taps g(0..r); g(-m) = g(m)
   float gsum[2 * FOBF_RMAX + 2];  // gsum[j] = sum_{m=-r}^{j-r-1} g(m), j=0..2r+1
+  // debug-check builds (FOBF_CHECKS): the device word collecting violation
+  // bits, and the workspace of a workspace-form launch (else null / 0)
+  unsigned int* check;
+  const float* ws;
+  long long ws_floats;
 };
+
+// Debug-check builds: the current device's violation word (allocated and
+// cleared on first use); null in release builds or when it cannot be made.
+unsigned int* check_word();
 
 // Fill an ImageParams from API arguments (validated by the caller).
 void make_params(ImageParams& p, const float* in, float* out, int H, int W,

@@ -25,10 +25,11 @@ __global__ __launch_bounds__(MTHREADS, (SH <= 20 ? 2 : 1)) void mfma_f32_kernel(
   float* Bt = lds + LDS_TABLE;
   float* At = Bt + 4 * DV * 64;
   float* nd = At + 4 * DV * 64;
+  const Img im = FOBF_IMG(p);
+  poison_lds(im);
   FOBF_LOAD_TABLES(p, tbl);
   __syncthreads();
-  build_f32_tables<SH>(tbl, p.r, Bt, At);
-  const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
+  build_f32_tables<SH>(im, tbl, p.r, Bt, At);
   __syncthreads();
   f32_tile<SH>(im, tx, ty, nblk, tbl, Bt, At, nd);
 }
@@ -45,8 +46,9 @@ __global__ __launch_bounds__((64 * staged_waves<OT, DV>())) void mfma_staged_ker
   float* tbl = lds;
   typename Stage<OT>::T* sbuf = reinterpret_cast<typename Stage<OT>::T*>(lds + LDS_TABLE);
   float* nd = lds + LDS_TABLE + staged_buf_bytes<OT, DV, NW>() / sizeof(float);
+  const Img im = FOBF_IMG(p);
+  poison_lds(im);
   FOBF_LOAD_TABLES(p, tbl);
-  const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
   __syncthreads();
   staged_tile<OT, DV, NW>(im, tx, ty, nblk, tbl, sbuf, nd);
 }
@@ -61,8 +63,10 @@ fobf_status launch_f32_sh(const ImageParams& p, int nblk, void* stream) {
   const size_t lds = sizeof(float) * (LDS_TABLE + 8 * DV * 64 +
                                       static_cast<size_t>(MWAVES) * 2 * nblk * 256);
   dim3 grid(padded_blocks(p, nblk));
+  ImageParams q = p;
+  q.lds_bytes = static_cast<int>(lds);
   hipLaunchKernelGGL(mfma_f32_kernel<SH>, grid, dim3(MTHREADS), lds,
-                     static_cast<hipStream_t>(stream), p, nblk);
+                     static_cast<hipStream_t>(stream), q, nblk);
   return check_launch("mfma_f32_kernel");
 }
 
@@ -86,8 +90,10 @@ fobf_status launch_staged_dv(const ImageParams& p, int nblk, void* stream) {
   nblk = std::min(nblk, cap);
   const size_t lds = fixed + sizeof(float) * NW * 2 * nblk * 256;
   dim3 grid(padded_blocks(p, nblk, NW));
+  ImageParams q = p;
+  q.lds_bytes = static_cast<int>(lds);
   hipLaunchKernelGGL((mfma_staged_kernel<OT, DV>), grid, dim3(64 * NW), lds,
-                     static_cast<hipStream_t>(stream), p, nblk);
+                     static_cast<hipStream_t>(stream), q, nblk);
   return check_launch("mfma_staged_kernel");
 }
 

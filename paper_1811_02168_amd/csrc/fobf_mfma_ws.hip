@@ -29,8 +29,9 @@ __global__ __launch_bounds__((64 * staged_waves<OT, DV>())) void mfma_staged_ws_
   float* tbl = lds;
   typename Stage<OT>::T* sbuf = reinterpret_cast<typename Stage<OT>::T*>(lds + LDS_TABLE);
   float* nd = work + (static_cast<size_t>(ty) * ntx + tx) * (NW * 2 * 256) * nblk;
+  const Img im = FOBF_IMG(p);
+  poison_lds(im);
   FOBF_LOAD_TABLES(p, tbl);
-  const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
   __syncthreads();
   staged_tile<OT, DV, NW, true>(im, tx, ty, nblk, tbl, sbuf, nd);
 }
@@ -52,10 +53,11 @@ __global__ __launch_bounds__(64 * kWsWaves) void mfma_f32_ws_kernel(ImageParams 
   float* sbuf = At + 4 * DV * 64;
   const int PC = f32s_pitch(SH, NW, p.r, stage_item_width<DV, NW>());
   float* nd = work + (static_cast<size_t>(ty) * ntx + tx) * (NW * 2 * 256) * nblk;
+  const Img im = FOBF_IMG(p);
+  poison_lds(im);
   FOBF_LOAD_TABLES(p, tbl);
   __syncthreads();
-  build_f32_tables<SH>(tbl, p.r, Bt, At);
-  const Img im{p.in, p.out, p.H, p.W, p.ld_in, p.ld_out, p.r, p.K, p.inv_period};
+  build_f32_tables<SH>(im, tbl, p.r, Bt, At);
   __syncthreads();
   f32s_tile<SH, NW>(im, tx, ty, nblk, tbl, Bt, At, sbuf, PC, nd);
 }
@@ -69,8 +71,10 @@ fobf_status launch_staged_ws_dv(const ImageParams& p, int nblk, float* work, voi
   constexpr size_t lds = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV, NW, true>();
   static_assert(lds <= 160 * 1024, "staging buffers exceed the LDS");
   dim3 grid(padded_blocks(p, nblk, NW));
+  ImageParams q = p;
+  q.lds_bytes = static_cast<int>(lds);
   hipLaunchKernelGGL((mfma_staged_ws_kernel<OT, DV>), grid, dim3(64 * NW), lds,
-                     static_cast<hipStream_t>(stream), p, nblk, work);
+                     static_cast<hipStream_t>(stream), q, nblk, work);
   return check_launch("mfma_staged_ws_kernel");
 }
 
@@ -84,8 +88,10 @@ fobf_status launch_f32_ws_sh(const ImageParams& p, int nblk, float* work, void* 
                                       2 * static_cast<size_t>(kF32Ch) * 16 * PC);
   if (lds > 160 * 1024) return fail(FOBF_EINTERNAL, "fobf_filter_ws: staging exceeds the LDS");
   dim3 grid(padded_blocks(p, nblk, kWsWaves));
+  ImageParams q = p;
+  q.lds_bytes = static_cast<int>(lds);
   hipLaunchKernelGGL(mfma_f32_ws_kernel<SH>, grid, dim3(64 * kWsWaves), lds,
-                     static_cast<hipStream_t>(stream), p, nblk, work);
+                     static_cast<hipStream_t>(stream), q, nblk, work);
   return check_launch("mfma_f32_ws_kernel");
 }
 
@@ -141,10 +147,13 @@ size_t ws_bytes(const ImageParams& p, int prec) {
   return sizeof(float) * ntx * nty * kWsWaves * 2 * 256 * static_cast<size_t>(nblk);
 }
 
-fobf_status launch_mfma_ws(const ImageParams& p, int prec, float* work, void* stream) {
-  const int nblk = ws_nblk(p, prec);
-  const int DV = (MSTRIP + 2 * p.r + 15) / 16;
+fobf_status launch_mfma_ws(const ImageParams& p0, int prec, float* work, void* stream) {
+  const int nblk = ws_nblk(p0, prec);
+  const int DV = (MSTRIP + 2 * p0.r + 15) / 16;
   if (nblk == 0) return fail(FOBF_EINTERNAL, "fobf_filter_ws: no workspace form");
+  ImageParams p = p0;   // the workspace extent, for the debug-check build
+  p.ws = work;
+  p.ws_floats = static_cast<long long>(ws_bytes(p0, prec) / sizeof(float));
   if (prec == FOBF_FP32) {
     static const auto table =
         f32_ws_table(std::make_integer_sequence<int, kWsMaxSH - kWsMinSH + 1>{});

@@ -42,6 +42,10 @@
 
 #include "fobf_internal.h"
 
+#ifndef FOBF_CHECKS
+#define FOBF_CHECKS 0
+#endif
+
 namespace fobf {
 namespace {
 
@@ -95,7 +99,132 @@ struct Img {
   float* __restrict__ out;
   int H, W, ld_in, ld_out, r, K;
   float inv_period;
+#if FOBF_CHECKS
+  unsigned int* check;
+  const float* ws;
+  long long ws_floats;
+  int lds_bytes;
+#endif
 };
+
+// The Img of a parameter block.  A macro for the reason FOBF_LOAD_TABLES is
+// one (the block is indexed where it is, never passed by address).
+#if FOBF_CHECKS
+#define FOBF_IMG(p)                                                                   \
+  Img{(p).in, (p).out, (p).H, (p).W, (p).ld_in, (p).ld_out, (p).r, (p).K,             \
+      (p).inv_period, (p).check, (p).ws, (p).ws_floats, (p).lds_bytes}
+#else
+#define FOBF_IMG(p)                                                                   \
+  Img{(p).in, (p).out, (p).H, (p).W, (p).ld_in, (p).ld_out, (p).r, (p).K, (p).inv_period}
+#endif
+
+// ---- debug-check builds (FOBF_CHECKS = 1) --------------------------------
+// Every check reads only: a failed one ORs its FOBF_CHECK_* bit into the
+// image's violation word (a vector atomic) and the kernel carries on, so
+// the checked kernels compute what the release kernels compute.  In
+// release builds all of this compiles to nothing.
+#if FOBF_CHECKS
+#define FOBF_CHK(im, cond, bit)                                     \
+  do {                                                              \
+    if (!(cond) && (im).check) atomicOr((im).check, (bit));         \
+  } while (0)
+#else
+#define FOBF_CHK(im, cond, bit) \
+  do {                          \
+  } while (0)
+#endif
+
+// `bytes` at p lie inside the launch's dynamic LDS allocation.
+__device__ __forceinline__ void chk_lds(const Img& im, const void* p, int bytes) {
+#if FOBF_CHECKS
+  extern __shared__ float fobf_dyn_lds[];
+  const long long off =
+      static_cast<const char*>(p) - reinterpret_cast<const char*>(fobf_dyn_lds);
+  FOBF_CHK(im, off >= 0 && off + bytes <= im.lds_bytes, FOBF_CHECK_LDS);
+#endif
+}
+
+// (row, col) is a pixel of the image.
+__device__ __forceinline__ void chk_img(const Img& im, int row, int col) {
+  FOBF_CHK(im,
+           row >= 0 && row < im.H && col >= 0 && col < im.W && col < im.ld_in,
+           FOBF_CHECK_IMAGE);
+}
+
+// n floats at p lie inside the workspace (workspace forms) or the LDS
+// allocation (N and D in LDS).
+__device__ __forceinline__ void chk_nd(const Img& im, const float* p, int n) {
+#if FOBF_CHECKS
+  if (im.ws)
+    FOBF_CHK(im, p >= im.ws && p + n <= im.ws + im.ws_floats, FOBF_CHECK_WS);
+  else
+    chk_lds(im, p, 4 * n);
+#endif
+}
+
+// A non-zero horizontal tap w joins window column c (counted from the
+// first column of the strip's window, x0w - r) to output column n of the
+// strip only within the output's window: 0 <= c - n <= 2r.
+__device__ __forceinline__ void chk_htap(const Img& im, float w, int c, int n) {
+  FOBF_CHK(im, w == 0.f || (c - n >= 0 && c - n <= 2 * im.r), FOBF_CHECK_HALO_H);
+}
+// the same for a vertical tap joining ring row h (counted from the first
+// row of the output block's window) to output row m of the block
+__device__ __forceinline__ void chk_vtap(const Img& im, float w, int h, int m) {
+  FOBF_CHK(im, w == 0.f || (h - m >= 0 && h - m <= 2 * im.r), FOBF_CHECK_HALO_V);
+}
+
+// The float32 Toeplitz slices as every reader indexes them (lane's Bt[s]
+// for window column SH (lane/16) + s, At[4d + v] for ring row 16 d + 4
+// (lane/16) + v, against output column / row lane%16): in the LDS, and
+// non-zero only inside the windows.  Once per channel group: the readers
+// index them the same way for every block.
+template <int SH>
+__device__ __forceinline__ void chk_f32_tables(const Img& im, const float* Bt, const float* At,
+                                               int lane) {
+#if FOBF_CHECKS
+  constexpr int DV = (SH + 3) / 4;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 1
+  for (int s = 0; s < 4 * DV; ++s) {
+    chk_lds(im, Bt + s * 64 + lane, 4);
+    chk_lds(im, At + s * 64 + lane, 4);
+    if (s < SH) chk_htap(im, Bt[s * 64 + lane], SH * lk + s, li);
+    chk_vtap(im, At[s * 64 + lane], 16 * (s >> 2) + 4 * lk + (s & 3), li);
+  }
+#endif
+}
+
+// Which horizontal block each slot of a vertical ring holds (check builds
+// only): the vertical pass of output block pb must find block pb + d in
+// the slot it takes for its d-th block.
+template <int DV>
+struct RingTags {
+#if FOBF_CHECKS
+  int q[DV];
+  __device__ __forceinline__ void set(int u, int v) { q[u] = v; }
+  __device__ __forceinline__ void check(const Img& im, int slot, int want) const {
+    FOBF_CHK(im, q[slot] == want, FOBF_CHECK_RING);
+  }
+#else
+  __device__ __forceinline__ void set(int, int) {}
+  __device__ __forceinline__ void check(const Img&, int, int) const {}
+#endif
+};
+
+// Fills the launch's dynamic LDS with all-ones words (NaN in float32, fp16
+// and bf16) from `from_bytes` on, then waits for the workgroup: a later
+// read of a word the kernel never wrote carries NaN into the output.
+__device__ __forceinline__ void poison_lds(const Img& im, int from_bytes = 0) {
+#if FOBF_CHECKS
+  extern __shared__ float fobf_dyn_lds[];
+  uint32_t* w = reinterpret_cast<uint32_t*>(fobf_dyn_lds);
+  for (int i = from_bytes / 4 + static_cast<int>(threadIdx.x); i < im.lds_bytes / 4;
+       i += blockDim.x)
+    w[i] = 0xffffffffu;
+  __syncthreads();
+#endif
+}
 
 // Copies the image's tables into LDS.  A macro, not a function: the kernel
 // parameter block must be indexed in the kernel body itself (taking its
@@ -159,6 +288,8 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
   auto load_block = [&](int q, float (&v)[SH]) {
     if (!EDGE) {
       const float* p = rowptr(q);
+      chk_img(im, y0 - r + 16 * q + li, colbase);
+      chk_img(im, y0 - r + 16 * q + li, colbase + SH - 1);
 #pragma unroll
       for (int s = 0; s < SH; ++s) v[s] = p[s];
     } else {
@@ -170,6 +301,8 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
   };
 
   f4 ring[DV][G];
+  RingTags<DV> tags;
+  chk_f32_tables<SH>(im, Bt, At, lane);
   float fv[SH];
   load_block(0, fv);
 
@@ -188,6 +321,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
+            chk_img(im, gy, gxo);
             fo[v] = im.in[gy * ld + gxo];
           }
           __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
@@ -197,6 +331,10 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
         const int rown = y0 - r + 16 * qn + li;
         const float* pn = EDGE ? im.in + static_cast<size_t>(min(max(rown, 0), im.H - 1)) * ld
                                : rowptr(qn);
+        if (!EDGE) {
+          chk_img(im, rown, colbase);
+          chk_img(im, rown, colbase + SH - 1);
+        }
         // ---- horizontal pass, H rows 16q .. 16q+15 of the strip ----
         const int row = y0 - r + 16 * q + li;
         const bool rin = !EDGE || static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
@@ -232,6 +370,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) ring[u][g] = acc[g];
+        tags.set(u, q);
 
         // ---- vertical pass, output block pb ----
         if (pb >= 0) {
@@ -241,6 +380,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
 #pragma unroll
           for (int d = 0; d < DV; ++d) {
             const int slot = (u + 1 + d) % DV;
+            tags.check(im, slot, pb + d);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const float av = At[(d * 4 + v) * 64 + lane];
@@ -261,6 +401,8 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
             nv[v] = nrow[64 * v];
             if (G == 4) dv[v] = drow[64 * v];
           }
+          chk_nd(im, nrow, 193);
+          chk_nd(im, drow, 193);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             if (G == 1) {
@@ -308,6 +450,8 @@ __device__ __forceinline__ void init_nd(const Img& im, const float* tbl, int x0w
     for (int v = 0; v < 4; ++v) {
       const float wy = edge_weight(sS, y0 + 16 * pb + 4 * (lane >> 4) + v, im.H, im.r);
       const int idx = (pb * 4 + v) * 64 + lane;
+      chk_nd(im, Ns + idx, 1);
+      chk_nd(im, Ds + idx, 1);
       Ns[idx] = 0.f;
       Ds[idx] = cS[0] * wx * wy;
     }
@@ -322,8 +466,12 @@ __device__ __forceinline__ void store_nd(const Img& im, int x0w, int y0, int nbl
     for (int v = 0; v < 4; ++v) {
       const int gy = y0 + 16 * pb + 4 * (lane >> 4) + v;
       const int idx = (pb * 4 + v) * 64 + lane;
-      if (gy < im.H && gx < im.W)
+      if (gy < im.H && gx < im.W) {
+        chk_nd(im, Ns + idx, 1);
+        chk_nd(im, Ds + idx, 1);
+        FOBF_CHK(im, gy >= 0 && gx >= 0 && gx < im.ld_out, FOBF_CHECK_OUT);
         im.out[static_cast<size_t>(gy) * im.ld_out + gx] = Ns[idx] / Ds[idx] + shift;
+      }
     }
 }
 
@@ -332,10 +480,13 @@ __device__ __forceinline__ void store_nd(const Img& im, int x0w, int y0, int nbl
 // entries, those beyond SH unused) and At[d*4+v][lane] (vertical, DV blocks
 // x 4 rows).
 template <int SH>
-__device__ __forceinline__ void build_f32_tables(const float* gS, int r, float* Bt, float* At) {
+__device__ __forceinline__ void build_f32_tables(const Img& im, const float* gS, int r, float* Bt,
+                                                 float* At) {
   constexpr int DV = (SH + 3) / 4;
   for (int i = threadIdx.x; i < 4 * DV * 64; i += blockDim.x) {
     const int s = i >> 6, l = i & 63;
+    chk_lds(im, Bt + i, 4);
+    chk_lds(im, At + i, 4);
     Bt[i] = tap(gS, SH * (l >> 4) + s - r - (l & 15), r);
     const int d = s >> 2, v = s & 3;
     At[i] = tap(gS, 16 * d + 4 * (l >> 4) + v - r - (l & 15), r);
@@ -437,7 +588,10 @@ struct Stage<__bf16> {
   // and lo the remainder x - hi (exact in float32) rounded to bf16: the
   // pair still carries x to ~2^-17 relative, with fewer conversions than
   // rounding hi first.
+  // (remainders subtracted as written: never fused with the product that
+  // made x, so every build of the kernel splits a value the same way)
   __device__ static __forceinline__ void pack2(float x0, float x1, uint32_t (&w)[2]) {
+#pragma clang fp contract(off)
     typedef __bf16 b2 __attribute__((ext_vector_type(2)));
     const uint32_t u0 = __builtin_bit_cast(uint32_t, x0);
     const uint32_t u1 = __builtin_bit_cast(uint32_t, x1);
@@ -469,6 +623,7 @@ struct Stage<F16Pair> {
   }
   __device__ static __forceinline__ _Float16 cvt(float x) { return static_cast<_Float16>(x); }
   __device__ static __forceinline__ void pack2(float x0, float x1, uint32_t (&w)[2]) {
+#pragma clang fp contract(off)
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     const h2 hi = {static_cast<_Float16>(x0), static_cast<_Float16>(x1)};
     const h2 lo = {static_cast<_Float16>(x0 - static_cast<float>(hi[0])),
@@ -576,6 +731,8 @@ __device__ __forceinline__ void stage_fetch(const Img& im, int x0, int row0, int
   const int col0 = x0 - im.r + (it - rr * per_row) * IW;
   if (interior) {
     const float* p = im.in + static_cast<size_t>(row) * im.ld_in + col0;
+    chk_img(im, row, col0);
+    chk_img(im, row, col0 + IW - 1);
 #pragma unroll
     for (int j = 0; j < IW; ++j) fv[j] = p[j];
   } else {
@@ -616,7 +773,10 @@ __device__ __forceinline__ void stage_block(const Img& im, int k, float shift, i
     fs[j] = in[j] ? fvs[j] - shift : 0.f;     // f - m, zero outside
   }
   // IW is even and c0 a multiple of IW: pairs of words are 4-byte aligned
+  FOBF_CHK(im, rr < 16 && c0 + IW <= PC, FOBF_CHECK_STAGE);
   auto put = [&](int g, const float (&x)[IW]) {
+    chk_lds(im, buf + (g * 16 + rr) * PC + c0, IW * sizeof(typename S::T));
+    chk_lds(im, buf + (((NP - 1) * SCH + g) * 16 + rr) * PC + c0, IW * sizeof(typename S::T));
 #pragma unroll
     for (int j = 0; j < IW / 2; ++j) {
       uint32_t w[NP];
@@ -704,6 +864,9 @@ __device__ __forceinline__ void f32s_stage(const Img& im, float kinv, int x0, in
     }
   }
   // IW is even and c0 a multiple of it: pairs are 8-byte aligned
+  FOBF_CHK(im, rr < 16 && c0 + IW <= PC, FOBF_CHECK_STAGE);
+  chk_lds(im, buf + rr * PC + c0, 4 * IW);
+  chk_lds(im, buf + ((G - 1) * 16 + rr) * PC + c0, 4 * IW);
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -748,6 +911,10 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
   const size_t ld = static_cast<size_t>(im.ld_in);
 
   f4 ring[DV][G];
+  RingTags<DV> tags;
+  // (check builds) the slices, and the last column a lane's steps read
+  chk_f32_tables<SH>(im, Bt, At, lane);
+  FOBF_CHK(im, 16 * wave + SH * lk + SH <= PC, FOBF_CHECK_HALO_H);
   float fvs[IW];
   stage_fetch<IW>(im, x0, y0 - r, CWn, block_interior(y0 - r), fvs);
   __syncthreads();   // the previous group's readers are done with both buffers
@@ -766,11 +933,14 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
             nv[v] = Ns[pb * 256 + 64 * v + lane];
             if (HK) dv[v] = Ds[pb * 256 + 64 * v + lane];
           }
+          chk_nd(im, Ns + pb * 256 + lane, 193);
+          chk_nd(im, Ds + pb * 256 + lane, 193);
         }
         if (HK) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
+            chk_img(im, gy, gxo);
             fo[v] = im.in[gy * ld + gxo];
           }
         }
@@ -791,6 +961,8 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
 #pragma unroll
         for (int g = 0; g < G; ++g)
           ag[g] = PIN ? lds_pinned(arow + g * 16 * PC) : arow + g * 16 * PC;
+        chk_lds(im, ag[0], 4);
+        chk_lds(im, ag[G - 1] + SH - 1, 4);
         f4 acc[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
@@ -803,6 +975,7 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) ring[u][g] = acc[g];
+        tags.set(u, q);
         // ---- vertical pass, output block pb ----
         if (pb >= 0) {
           f4 vacc[G];
@@ -811,6 +984,7 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
 #pragma unroll
           for (int d = 0; d < DV; ++d) {
             const int slot = (u + 1 + d) % DV;
+            tags.check(im, slot, pb + d);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const float av = TREG ? atr[d * 4 + v] : At[(d * 4 + v) * 64 + lane];
@@ -859,7 +1033,10 @@ __device__ __forceinline__ void f32s_tile(const Img& im, int tx, int ty, int nbl
   {
     float4* z = reinterpret_cast<float4*>(sbuf);
     const int n16 = 2 * kF32Ch * 16 * PC / 4;
-    for (int i = threadIdx.x; i < n16; i += 64 * NW) z[i] = float4{0.f, 0.f, 0.f, 0.f};
+    for (int i = threadIdx.x; i < n16; i += 64 * NW) {
+      chk_lds(im, z + i, 16);
+      z[i] = float4{0.f, 0.f, 0.f, 0.f};
+    }
   }
   init_nd(im, tbl, x0 + wave * MSTRIP, y0, nblk, Ns, Ds, lane);
   constexpr int DV = (SH + 3) / 4;
@@ -970,7 +1147,10 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
         for (int d = 0; d < DV; ++d)
 #pragma unroll
-          for (int h = 0; h < NS; ++h) vtap4[(d * NS + h) * 64 + lane] = Aw4[d][h];
+          for (int h = 0; h < NS; ++h) {
+            chk_lds(im, vtap4 + (d * NS + h) * 64 + lane, sizeof(o4));
+            vtap4[(d * NS + h) * 64 + lane] = Aw4[d][h];
+          }
     } else {
 #pragma unroll
       for (int t = 0; t < NV; ++t)
@@ -985,11 +1165,57 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
         for (int t = 0; t < NV; ++t)
 #pragma unroll
-          for (int h = 0; h < NS; ++h) vtap[(t * NS + h) * 64 + lane] = Aw[t][h];
+          for (int h = 0; h < NS; ++h) {
+            chk_lds(im, vtap + (t * NS + h) * 64 + lane, sizeof(v8));
+            vtap[(t * NS + h) * 64 + lane] = Aw[t][h];
+          }
     }
   }
 
   o4 ring[DV][NS][G];
+  RingTags<DV> tags;
+  // check builds: the horizontal reads of step s (columns 16 wave + 32 s +
+  // 8 lk + 0..7 of buffer row li) stay in the row and in the LDS, and the
+  // taps they meet join them to output columns inside their windows
+  FOBF_CHK(im, 16 * wave + 32 * (SHS - 1) + 8 * lk + 8 <= PC, FOBF_CHECK_HALO_H);
+#if FOBF_CHECKS
+#pragma unroll
+  for (int s = 0; s < SHS; ++s)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      chk_htap(im, static_cast<float>(Bw[s][0][j]), 32 * s + 8 * lk + j, li);
+#endif
+  auto chk_hread = [&](const typename S::T* rowp, int s) {
+    if (s == 0 || s == SHS - 1) chk_lds(im, rowp, 8 * sizeof(typename S::T));
+  };
+  // check builds: the vertical taps met by ring block d (K = 16 operand:
+  // element j <-> H row 16 d + 4 lk + j; K = 32 operand t: element j <->
+  // H row 16 (2t + j/4) + 4 lk + j%4), and the blocks the slots hold
+  // (the taps once per group, as every block reads them; the slots per
+  // block)
+#if FOBF_CHECKS
+  if (!kVtapLds || wave == 0) {
+    if constexpr (GND) {
+#pragma unroll
+      for (int d = 0; d < DV; ++d)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          chk_vtap(im, static_cast<float>(Aw4[d][0][j]), 16 * d + 4 * lk + j, li);
+    } else {
+#pragma unroll
+      for (int t = 0; t < NV; ++t)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          chk_vtap(im, static_cast<float>(Aw[t][0][j]),
+                   16 * (2 * t + (j >> 2)) + 4 * lk + (j & 3), li);
+    }
+  }
+#endif
+  auto chk_vread4 = [&](const o4&, int d, int slot, int pb) { tags.check(im, slot, pb + d); };
+  auto chk_vread8 = [&](const v8&, int t, int slot0, int slot1, int pb) {
+    tags.check(im, slot0, pb + 2 * t);
+    if (2 * t + 1 < DV) tags.check(im, slot1, pb + 2 * t + 1);
+  };
   auto block_interior = [&](int row0) { return cols_in && row0 >= 0 && row0 + 16 <= im.H; };
   float fvs[IW];
   stage_fetch<IW>(im, x0, y0 - r, CWn, block_interior(y0 - r), fvs);
@@ -1014,12 +1240,15 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
             nv[v] = Ns[pb * 256 + 64 * v + lane];
             if (NF > 0) dv[v] = Ds[pb * 256 + 64 * v + lane];
           }
+          chk_nd(im, Ns + pb * 256 + lane, 193);
+          chk_nd(im, Ds + pb * 256 + lane, 193);
         }
         if (NF > 0) {
           const int gx = min(x0w + li, im.W - 1);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
+            chk_img(im, gy, gx);
             fo[v] = im.in[static_cast<size_t>(gy) * im.ld_in + gx];
           }
         }
@@ -1041,6 +1270,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
           for (int g = 0; g < G; ++g) {
             v8 a[NS];
+            if (g == 0) chk_hread(buf + li * PC + 16 * wave + 32 * s + 8 * lk, s);
 #pragma unroll
             for (int h = 0; h < NS; ++h)
               a[h] = *reinterpret_cast<const v8*>(buf + ((h * SCH + g) * 16 + li) * PC +
@@ -1062,6 +1292,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
             if (NS == 2)
               ring[u][NS - 1][g][v] = S::cvt(acc[g][v] - static_cast<float>(ring[u][0][g][v]));
           }
+        tags.set(u, q);
 
         // ---- vertical pass, output block pb = q - DV + 1 ----
         if (pb >= 0) {
@@ -1076,6 +1307,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
               for (int h = 0; h < NS; ++h)
                 aw[h] = kVtapLds ? vtap4[(d * NS + h) * 64 + lane] : Aw4[d][h];
+              chk_vread4(aw[0], d, slot, pb);
 #pragma unroll
               for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -1091,6 +1323,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
             v8 aw[NS];
 #pragma unroll
             for (int h = 0; h < NS; ++h) aw[h] = kVtapLds ? vtap[(t * NS + h) * 64 + lane] : Aw[t][h];
+            chk_vread8(aw[0], t, (u + 1 + b0) % DV, (u + 1 + b1) % DV, pb);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
               v8 b[NS];
@@ -1116,6 +1349,8 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
               nv[v] = nrow[64 * v];
               if (NF > 0) dv[v] = drow[64 * v];
             }
+            chk_nd(im, nrow, 193);
+            chk_nd(im, drow, 193);
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -1149,6 +1384,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
             for (int i = 0; i < gn; ++i) {
               v8 a[NS];
+              if (sg == 0 && i == 0) chk_hread(buf + li * PC + 16 * wave + 32 * s + 8 * lk, s);
 #pragma unroll
               for (int h = 0; h < NS; ++h)
                 a[h] = *reinterpret_cast<const v8*>(buf + ((h * SCH + gb + i) * 16 + li) * PC +
@@ -1169,6 +1405,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
                     S::cvt(acc[i][v] - static_cast<float>(ring[u][0][gb + i][v]));
             }
         }
+        tags.set(u, q);
         // one buffer: every wave is done reading it before the next block
         // is staged into it
         if (NBUF == 1) __syncthreads();
@@ -1185,6 +1422,8 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
               nv[v] = nrow[64 * v];
               if (NF > 0) dv[v] = drow[64 * v];
             }
+            chk_nd(im, nrow, 193);
+            chk_nd(im, drow, 193);
           }
 #pragma unroll
           for (int sg = 0; sg < NSG; ++sg) {
@@ -1200,6 +1439,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
                 for (int h = 0; h < NS; ++h)
                   aw[h] = kVtapLds ? vtap4[(d * NS + h) * 64 + lane] : Aw4[d][h];
+                if (sg == 0) chk_vread4(aw[0], d, slot, pb);
 #pragma unroll
                 for (int i = 0; i < gn; ++i)
 #pragma unroll
@@ -1216,6 +1456,7 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
                 for (int h = 0; h < NS; ++h)
                   aw[h] = kVtapLds ? vtap[(t * NS + h) * 64 + lane] : Aw[t][h];
+                if (sg == 0) chk_vread8(aw[0], t, (u + 1 + b0) % DV, (u + 1 + b1) % DV, pb);
 #pragma unroll
                 for (int i = 0; i < gn; ++i) {
                   v8 b[NS];
@@ -1280,11 +1521,15 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
   {
     float4* z = reinterpret_cast<float4*>(sbuf);
     const int n16 = static_cast<int>(staged_stage_bytes<OT, DV, NW, GND>() / 16);
-    for (int i = threadIdx.x; i < n16; i += 64 * NW) z[i] = float4{0.f, 0.f, 0.f, 0.f};
+    for (int i = threadIdx.x; i < n16; i += 64 * NW) {
+      chk_lds(im, z + i, 16);
+      z[i] = float4{0.f, 0.f, 0.f, 0.f};
+    }
   }
   // Staged channels carry (f - m) instead of f, m = f at the tile centre:
   // the numerator becomes N - m D exactly, so out = N'/D + m, and the
   // magnitudes rounded to the staging type shrink to the local contrast.
+  chk_img(im, min(y0 + TYo / 2, im.H - 1), min(x0 + NW * MSTRIP / 2, im.W - 1));
   const float shift = im.in[static_cast<size_t>(min(y0 + TYo / 2, im.H - 1)) * im.ld_in +
                             min(x0 + NW * MSTRIP / 2, im.W - 1)];
   init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);

@@ -20,6 +20,10 @@
 
 #include "fobf_internal.h"
 
+#ifndef FOBF_CHECKS
+#define FOBF_CHECKS 0
+#endif
+
 namespace fobf {
 namespace {
 
@@ -61,6 +65,20 @@ __global__ __launch_bounds__(VTHREADS) void valu_kernel(ImageParams p) {
   const int tid = threadIdx.x;
   const int x0 = blockIdx.x * VTX;
   const int y0 = blockIdx.y * VTY;
+#if FOBF_CHECKS
+  // debug-check build: LDS starts as NaN words; the sliding windows' last
+  // reads (row xb + 2r + 4 of the channel tile, row oy0 + 2r + 4 of the
+  // horizontal pass) stay inside the allocation
+  for (int i = tid; i < p.lds_bytes / 4; i += VTHREADS) reinterpret_cast<uint32_t*>(lds)[i] = ~0u;
+  __syncthreads();
+  if (p.check) {
+    const long long need = sizeof(float) * (static_cast<long long>(IH) * P + (IH + 4) * VTX +
+                                            2 * r + 1);
+    if (need > p.lds_bytes || VTX - 4 + 2 * r + 4 >= P ||
+        (VTY - 4) + 2 * r + 4 >= IH + 4)
+      atomicOr(p.check, FOBF_CHECK_LDS);
+  }
+#endif
   for (int m = tid; m <= 2 * r; m += VTHREADS) gS[m] = p.g[m <= r ? r - m : m - r];
 
   // output pixels of this thread: column ox, rows oy0 .. oy0+3
@@ -179,7 +197,12 @@ __global__ __launch_bounds__(VTHREADS) void valu_kernel(ImageParams p) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int gy = y0 + oy0 + i, gx = x0 + ox;
-    if (gy < p.H && gx < p.W) p.out[static_cast<size_t>(gy) * p.ld_out + gx] = N[i] / D[i];
+    if (gy < p.H && gx < p.W) {
+#if FOBF_CHECKS
+      if (p.check && gx >= p.ld_out) atomicOr(p.check, FOBF_CHECK_OUT);
+#endif
+      p.out[static_cast<size_t>(gy) * p.ld_out + gx] = N[i] / D[i];
+    }
   }
 }
 
@@ -192,8 +215,10 @@ fobf_status launch_valu(const ImageParams& p, void* stream) {
       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)attr;
   dim3 grid((p.W + VTX - 1) / VTX, (p.H + VTY - 1) / VTY);
+  ImageParams q = p;
+  q.lds_bytes = static_cast<int>(lds);
   hipLaunchKernelGGL(valu_kernel, grid, dim3(VTHREADS), lds,
-                     static_cast<hipStream_t>(stream), p);
+                     static_cast<hipStream_t>(stream), q);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess)
     return fail(FOBF_EHIP, std::string("valu_kernel launch: ") + hipGetErrorString(e));

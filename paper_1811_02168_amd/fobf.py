@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfobf.so")
+CHECK_LIB_PATH = os.path.join(HERE, "libfobf_check.so")
 
 KMAX = 32
 RMAX = 48
@@ -89,12 +90,12 @@ class _Result(C.Structure):
                 ("t_done", C.c_double), ("T", C.c_int), ("prec", C.c_int)]
 
 
-def _load():
-    if not os.path.exists(LIB_PATH):
+def _load(path=LIB_PATH):
+    if not os.path.exists(path):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it with "
+            f"{path} is missing: build it with "
             "`python paper_1811_02168_amd/build.py` (no CPU fallback exists)")
-    lib = C.CDLL(LIB_PATH)
+    lib = C.CDLL(path)
     lib.fobf_fit.argtypes = [C.c_int, C.c_double, C.c_int, C.c_double, C.c_int,
                              C.POINTER(_Coef)]
     lib.fobf_fit_samples.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int,
@@ -152,6 +153,7 @@ def _load():
     bind("fobf_lut_save", [C.c_void_p, C.c_char_p])
     bind("fobf_lut_load", [C.c_char_p, C.POINTER(C.c_void_p)])
     bind("fobf_lut_destroy", [C.c_void_p], None)
+    bind("fobf_check_take", [C.POINTER(C.c_uint)])
     lib.fobf_last_error.restype = C.c_char_p
     lib.fobf_fit.restype = C.c_int
     lib.fobf_fit_samples.restype = C.c_int
@@ -160,6 +162,32 @@ def _load():
 
 
 lib = _load()
+
+
+def load_check_library():
+    """The debug-check build (libfobf_check.so: LDS poisoning and index
+    checks), bound like `lib`.  Route this module's calls through it by
+    rebinding `lib` (tests do so), and read its violations with
+    check_take(that_library)."""
+    return _load(CHECK_LIB_PATH)
+
+
+def check_take(library=None) -> int:
+    """Violation bits (FOBF_CHECK_*) recorded by a debug-check library since
+    the last call, cleared; waits for the device.  Raises FobfError on the
+    release library."""
+    L = library or lib
+    bits = C.c_uint(0)
+    st = L.fobf_check_take(C.byref(bits))
+    if st != OK:
+        m = L.fobf_last_error()
+        raise FobfError(st, m.decode() if m else "")
+    return int(bits.value)
+
+
+CHECK_BITS = {"lds": 0x001, "image": 0x002, "halo_h": 0x004, "halo_v": 0x008,
+              "ring": 0x010, "ws": 0x020, "out": 0x040, "tile": 0x080,
+              "stage": 0x100}
 
 
 def last_error() -> str:

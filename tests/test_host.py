@@ -38,6 +38,25 @@ def test_library_exports_header_symbols():
     assert "fobf_peak" in names and "fobf_fit_cache_clear" in names
 
 
+def test_check_library_exports_and_release_refuses():
+    """The debug-check twin exports the same symbols; fobf_check_take says
+    which build it is without touching a device (release: EINVAL)."""
+    import ctypes as C
+    import paper_1811_02168_amd as F
+    chk = F.load_check_library()
+    missing = [n for n in header_functions() if not hasattr(chk, n)]
+    assert not missing, missing
+    bits = C.c_uint(7)
+    assert F.lib.fobf_check_take(C.byref(bits)) == F.fobf.EINVAL
+    assert bits.value == 0
+    assert "without FOBF_CHECKS" in F.last_error()
+    assert F.lib.fobf_check_take(None) == F.fobf.EINVAL
+    assert chk.fobf_check_take(None) == F.fobf.EINVAL
+    with pytest.raises(F.FobfError):
+        F.check_take()
+    assert sorted(F.CHECK_BITS.values()) == [1 << i for i in range(9)]
+
+
 def test_peak_rejects_bad_arguments():
     import ctypes as C
     import paper_1811_02168_amd as F
