@@ -8,7 +8,10 @@
 // next of a few HIP streams ("lanes"): per request a stream-ordered device
 // allocation and the host-to-device copy, then ONE persistent batched
 // launch for all of them (fobf_filter_batch's kernel), then the copies back
-// and stream-ordered frees.  A host callback at the end of each batch marks
+// and stream-ordered frees.  A request large enough for the workspace form
+// of the filter (tall tiles, N and D in a workspace: the fobf_filter_ws
+// condition) runs that form instead, one launch of its own on the same
+// lane after the batch, its workspace drawn from the same pool.  A host callback at the end of each batch marks
 // its requests done and returns their bytes to the budget, which lets the
 // scheduler admit more: requests that arrive while others are on the
 // device join the next batch as soon as memory frees up, and batches on
@@ -27,10 +30,11 @@
 // before its kernel (until the event has been seen complete), so no
 // kernel can read a row before its bytes have landed.
 //
-// Device memory: request images, and each batch's job table, come from a
-// memory pool private to the server whose release threshold is the HBM
-// budget (the process's default pool is left untouched); each request is
-// charged its two images plus one batch-workspace share against the budget.
+// Device memory: request images, each batch's job table and the workspace
+// of a request that runs the workspace form come from a memory pool private
+// to the server whose release threshold is the HBM budget (the process's
+// default pool is left untouched); each request is charged its two images
+// plus the larger of one batch-workspace share and its own workspace.
 //
 // Host image buffers should be pinned (hipHostMalloc, or torch's
 // pin_memory) for the copies to be asynchronous; pageable buffers work but
@@ -190,10 +194,18 @@ hipError_t device_alloc(fobf_server* s, void** p, size_t bytes, hipStream_t st) 
 }
 
 // Device bytes a request is charged against the budget: its input and
-// output images plus one batch-workspace share (job-table entry and the
-// launch counters), so that every batch's workspace is covered too.
-size_t request_bytes(int H, int W) {
-  return 2 * sizeof(float) * static_cast<size_t>(H) * W + batch_workspace_bytes(1);
+// output images plus the larger of one batch-workspace share (job-table
+// entry and the launch counters) and the N/D workspace of the workspace
+// form (zero where that form is not used; the same for every precision),
+// so that every batch's and every workspace launch's memory is covered.
+size_t request_bytes(int H, int W, double theta) {
+  ImageParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.H = H;
+  p.W = W;
+  p.r = spatial_radius(theta);
+  return 2 * sizeof(float) * static_cast<size_t>(H) * W +
+         std::max(batch_workspace_bytes(1), ws_bytes(p, FOBF_FP32));
 }
 
 // Coefficients of an admitted request (its fit has finished): the first
@@ -331,6 +343,12 @@ void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
   std::vector<Req*> bad;
   std::vector<fobf_job> jobs;
   std::vector<const float*> cdev;
+  struct Tall {
+    Req* q;
+    ImageParams p;
+    int prec;
+  };
+  std::vector<Tall> tall;   // requests that run the workspace form
   for (Req* q : adm) {
     q->res.t_start = t0;
     fobf_status cs = coefficients(s, q, st);
@@ -371,23 +389,49 @@ void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
     j.prec = effective_prec(q->r.prec, q->r.K, q->T, q->c);
     for (int k = 0; k < q->r.K; ++k) j.c[k] = q->c[k];
     q->res.prec = j.prec;
-    jobs.push_back(j);
-    cdev.push_back(q->c_dev);
     q->res.T = q->T;
     ok.push_back(q);
+    Tall t{q, {}, j.prec};
+    make_params(t.p, j.d_in, j.d_out, j.H, j.W, j.ld_in, j.ld_out, j.theta, j.K, j.T, q->c);
+    t.p.c_dev = q->c_dev;
+    if (ws_nblk(t.p, j.prec) > 0) {
+      tall.push_back(t);
+      continue;
+    }
+    jobs.push_back(j);
+    cdev.push_back(q->c_dev);
   }
   for (Req* q : bad) finish_now(s, {q}, q->res.status);
   if (ok.empty()) return;
   void* ws = nullptr;
-  const size_t wsb = batch_workspace_bytes(static_cast<int>(jobs.size()));
   fobf_status st_b = FOBF_OK;
-  if (device_alloc(s, &ws, wsb, st) != hipSuccess) {
-    st_b = fail(FOBF_ENOMEM, "fobf_serve: workspace allocation failed");
-  } else {
-    st_b = filter_batch_impl(jobs.data(), static_cast<int>(jobs.size()), ws, wsb, st, cdev.data());
+  if (!jobs.empty()) {
+    const size_t wsb = batch_workspace_bytes(static_cast<int>(jobs.size()));
+    if (device_alloc(s, &ws, wsb, st) != hipSuccess) {
+      st_b = fail(FOBF_ENOMEM, "fobf_serve: workspace allocation failed");
+    } else {
+      st_b = filter_batch_impl(jobs.data(), static_cast<int>(jobs.size()), ws, wsb, st,
+                               cdev.data());
+    }
+  }
+  // the batch's status belongs to its requests; a workspace-form request
+  // carries its own
+  std::unordered_map<Req*, fobf_status> own;
+  for (Tall& t : tall) {
+    void* w = nullptr;
+    fobf_status st_t;
+    if (device_alloc(s, &w, ws_bytes(t.p, t.prec), st) != hipSuccess) {
+      st_t = fail(FOBF_ENOMEM, "fobf_serve: workspace allocation failed");
+    } else {
+      st_t = launch_mfma_ws(t.p, t.prec, static_cast<float*>(w), st);
+      hipFreeAsync(w, st);
+    }
+    own[t.q] = st_t;
   }
   for (Req* q : ok) {
-    if (st_b == FOBF_OK) {
+    const auto it = own.find(q);
+    const fobf_status st_q = it != own.end() ? it->second : st_b;
+    if (st_q == FOBF_OK) {
       const size_t row = sizeof(float) * q->r.W;
       if (hipMemcpy2DAsync(q->r.h_out, sizeof(float) * q->r.ld_out, q->d_out, row, row,
                            q->r.H, hipMemcpyDeviceToHost, st) != hipSuccess) {
@@ -395,7 +439,7 @@ void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
         q->res.status = FOBF_EHIP;
       }
     } else {
-      q->res.status = st_b;
+      q->res.status = st_q;
     }
     hipFreeAsync(q->d_in, st);
     hipFreeAsync(q->d_out, st);
@@ -581,7 +625,7 @@ extern "C" fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad precision");
   if (!(req->deadline_s >= 0.0) || !std::isfinite(req->deadline_s))
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad deadline");
-  const size_t bytes = request_bytes(req->H, req->W);
+  const size_t bytes = request_bytes(req->H, req->W, req->theta);
   if (bytes > s->cfg.hbm_budget_bytes)
     return fail(FOBF_ENOMEM, "fobf_serve_submit: request larger than the HBM budget");
   Req* q = new Req();

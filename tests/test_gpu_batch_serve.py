@@ -280,6 +280,42 @@ def test_serve_mix_equals_alone():
             assert float(np.max(np.abs(outs[i] - ref))) <= tol
 
 
+def test_serve_tall_requests_run_the_workspace_form():
+    """Requests tall enough for the workspace form run it (a launch of their
+    own after the batch of the others): each result equals fobf_filter_ws
+    on the same image with the coefficients the server used, bit for bit,
+    and the small request sharing their batch equals its single launch."""
+    import torch
+    import paper_1811_02168_amd as F
+    reqs = [(workloads.voronoi_image(2048, 2048, 200, True, 31), 5.0, 40.0, 8, "fp32"),
+            (workloads.voronoi_image(2100, 2300, 200, True, 32), 8.0, 70.0, 6, "fp16x2"),
+            (workloads.voronoi_image(90, 130, 20, True, 33), 4.0, 30.0, 5, "fp16")]
+    outs = [np.zeros_like(r[0], dtype=np.float32) for r in reqs]
+    budget = 1 << 30
+    with F.Server(hbm_budget_bytes=budget, max_inflight=8, max_batch=8) as srv:
+        tickets = [srv.submit(f.astype(np.float32), o, th, sg, K, prec=p)
+                   for (f, th, sg, K, p), o in zip(reqs, outs)]
+        res = [srv.poll(t, wait=True) for t in tickets]
+        stats = srv.stats()
+    assert stats["peak_bytes_inflight"] <= budget and stats["failed"] == 0
+    for (f, theta, sigma, K, prec), o, (st, r) in zip(reqs, outs, res):
+        assert st == 0, F.last_error()
+        coef = served_coef(F, sigma, K, r.T)
+        H, W = f.shape
+        n = F.filter_workspace_size(H, W, theta, prec)
+        img = dev_img(f)
+        if H >= 2048:
+            assert n > 0
+            ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+            want = F.filter(img, theta, K, coef.T, coef.c, prec=prec, workspace=ws)
+            torch.cuda.synchronize()
+            assert np.array_equal(o, want.cpu().numpy()), (H, W, prec)
+        else:
+            assert n == 0
+            ref = single(F, img, theta, K, coef.T, coef.c, prec)
+            assert float(np.max(np.abs(o - ref))) <= TOL
+
+
 def test_serve_against_oracle_small():
     import paper_1811_02168_amd as F
     f = workloads.C1.image()[:120, :150].astype(np.float32)
@@ -378,9 +414,10 @@ def test_serve_coefficient_row_ordering_across_lanes():
     row is uploaded on the lane of its first batch, queued behind that
     lane's earlier work (two 4096^2 requests keep two lanes busy), while
     later batches with the same new key run on an idle lane.  Each of those
-    must wait for the upload: every output equals the single-image batch
-    launch of its request bit for bit (a read of the row before it lands
-    gives garbage or NaN)."""
+    must wait for the upload: every output equals, bit for bit, the launch
+    the server runs for its request -- the workspace form for the 4096^2
+    ones, the single-image batch launch for the others (a read of the row
+    before it lands gives garbage or NaN)."""
     import torch
     import paper_1811_02168_amd as F
     def pinned(a):
@@ -405,10 +442,16 @@ def test_serve_coefficient_row_ordering_across_lanes():
         assert st == 0, (i, F.last_error())
         coef = served_coef(F, s, K, r.T)
         img = dev_img(f)
-        ref = torch.full_like(img, -1.0)
-        F.filter_batch([F.make_job(img, ref, theta, K, coef.T, coef.c)])
+        n = F.filter_workspace_size(f.shape[0], f.shape[1], theta, "fp32")
+        if n > 0:
+            ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+            ref = F.filter(img, theta, K, coef.T, coef.c, workspace=ws)
+        else:
+            ref = torch.full_like(img, -1.0)
+            F.filter_batch([F.make_job(img, ref, theta, K, coef.T, coef.c)])
         torch.cuda.synchronize()
         ref = ref.cpu().numpy()
+        assert (n > 0) == (f.shape[0] == 4096), i
         assert np.all(np.isfinite(o)), i
         assert np.array_equal(o, ref), (i, float(np.nanmax(np.abs(o - ref))))
 
