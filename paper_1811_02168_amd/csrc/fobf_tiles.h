@@ -75,10 +75,10 @@ __device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
 // add per read); the reads through it then take their small constant
 // offsets in the instruction's offset fields.
 template <typename T>
-__device__ __forceinline__ const T* lds_pinned(const T* p) {
-  auto q = (__attribute__((address_space(3))) const T*)p;
+__device__ __forceinline__ T* lds_pinned(T* p) {
+  auto q = (__attribute__((address_space(3))) T*)p;
   asm("" : "+v"(q));
-  return (const T*)q;
+  return (T*)q;
 }
 
 __device__ __forceinline__ float tap(const float* gS, int d, int r) {
@@ -863,16 +863,17 @@ __device__ __forceinline__ void f32s_stage(const Img& im, float kinv, int x0, in
       x[g0 + 3][j] = in ? sn : 0.f;
     }
   }
-  // IW is even and c0 a multiple of it: pairs are 8-byte aligned
+  // IW is even and c0 a multiple of it: pairs are 8-byte aligned (the row
+  // pointer pinned: the writes then take their offsets in the instruction)
   FOBF_CHK(im, rr < 16 && c0 + IW <= PC, FOBF_CHECK_STAGE);
   chk_lds(im, buf + rr * PC + c0, 4 * IW);
   chk_lds(im, buf + ((G - 1) * 16 + rr) * PC + c0, 4 * IW);
+  float* const wrow = lds_pinned(buf + rr * PC + c0);
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int j = 0; j < IW / 2; ++j)
-      reinterpret_cast<float2*>(buf + (g * 16 + rr) * PC + c0)[j] =
-          float2{x[g][2 * j], x[g][2 * j + 1]};
+      reinterpret_cast<float2*>(wrow + g * 16 * PC)[j] = float2{x[g][2 * j], x[g][2 * j + 1]};
 }
 
 // One channel group over the workgroup's tile: per 16-row block the
@@ -909,6 +910,11 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
   const bool cols_in = x0 - r >= 0 && x0 - r + IW * ((CWn + IW - 1) / IW) <= im.W;
   auto block_interior = [&](int row0) { return cols_in && row0 >= 0 && row0 + 16 <= im.H; };
   const size_t ld = static_cast<size_t>(im.ld_in);
+  // the fold's pixel values: where every output row of the tile lies in
+  // the image, block pb's four rows are at a fixed stride from one base
+  // (blocks with pb < 0 fold nothing: they read block 0's)
+  const bool rows_in = y0 + 16 * nblk <= im.H;
+  const float* const fo_base = im.in + static_cast<size_t>(min(y0 + 4 * lk, im.H - 1)) * ld + gxo;
 
   f4 ring[DV][G];
   RingTags<DV> tags;
@@ -937,11 +943,18 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
           chk_nd(im, Ds + pb * 256 + lane, 193);
         }
         if (HK) {
+          if (rows_in) {
+            const float* const p = fo_base + static_cast<size_t>(16 * max(pb, 0)) * ld;
+            chk_img(im, y0 + 16 * max(pb, 0) + 4 * lk + 3, gxo);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
-            chk_img(im, gy, gxo);
-            fo[v] = im.in[gy * ld + gxo];
+            for (int v = 0; v < 4; ++v) fo[v] = p[v * ld];
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
+              chk_img(im, gy, gxo);
+              fo[v] = im.in[gy * ld + gxo];
+            }
           }
         }
         if (block_interior(row0))
@@ -1217,6 +1230,13 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
     if (2 * t + 1 < DV) tags.check(im, slot1, pb + 2 * t + 1);
   };
   auto block_interior = [&](int row0) { return cols_in && row0 >= 0 && row0 + 16 <= im.H; };
+  // the fold's pixel values: where every output row of the tile lies in
+  // the image, block pb's four rows are at a fixed stride from one base
+  // (blocks with pb < 0 fold nothing: they read block 0's)
+  const size_t ldi = static_cast<size_t>(im.ld_in);
+  const bool rows_in = y0 + 16 * nblk <= im.H;
+  const float* const fo_base =
+      im.in + static_cast<size_t>(min(y0 + 4 * lk, im.H - 1)) * ldi + min(x0w + li, im.W - 1);
   float fvs[IW];
   stage_fetch<IW>(im, x0, y0 - r, CWn, block_interior(y0 - r), fvs);
   __syncthreads();   // the previous group's readers are done with both buffers
@@ -1244,12 +1264,19 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
           chk_nd(im, Ds + pb * 256 + lane, 193);
         }
         if (NF > 0) {
-          const int gx = min(x0w + li, im.W - 1);
+          if (rows_in) {
+            const float* const p = fo_base + static_cast<size_t>(16 * max(pb, 0)) * ldi;
+            chk_img(im, y0 + 16 * max(pb, 0) + 4 * lk + 3, min(x0w + li, im.W - 1));
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
-            chk_img(im, gy, gx);
-            fo[v] = im.in[static_cast<size_t>(gy) * im.ld_in + gx];
+            for (int v = 0; v < 4; ++v) fo[v] = p[v * ldi];
+          } else {
+            const int gx = min(x0w + li, im.W - 1);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
+              chk_img(im, gy, gx);
+              fo[v] = im.in[static_cast<size_t>(gy) * ldi + gx];
+            }
           }
         }
         if (block_interior(row0))
