@@ -604,18 +604,21 @@ def batch_leg(F, torch, n):
     flop = sum(4 * (2 * math.ceil(3 * j.theta) + 1) * (4 * j.K - 3) * j.H * j.W
                for j in jobs)
     # matrix-core flops the fp32 batch body executes: per tile of 4 strips x
-    # nblk blocks, (nblk + DV - 1) horizontal and nblk vertical 16-row blocks,
-    # each 4 DV steps of a 16x16x4 product (2048 flop) per channel; at small
-    # radii the 16-column band of the Toeplitz products is mostly zero taps
-    # (r = 6: 32 columns for 13 taps)
+    # nblk blocks and per channel, (nblk + DV - 1) horizontal 16-row blocks
+    # of SH = ceil((16 + 2r) / 4) steps and nblk vertical blocks of 4 DV
+    # steps, each step a 16x16x4 product (2048 flop); at small radii the
+    # 16-column band of the Toeplitz products is mostly zero taps (r = 6:
+    # 28 columns and 32 rows for 13 taps)
     exec_flop = 0
     for j in jobs:
         r = math.ceil(3 * j.theta)
         dv = (16 + 2 * r + 15) // 16
+        sh = (16 + 2 * r + 3) // 4
         nblk = F.tune_get("fp32", j.theta)[1]
         nblk = max(1, min(nblk, 8, (j.H + 15) // 16))
         ntx, nty = -(-j.W // 64), -(-j.H // (16 * nblk))
-        exec_flop += ntx * nty * 4 * 2048 * (4 * j.K - 3) * 4 * dv * (2 * nblk + dv - 1)
+        exec_flop += (ntx * nty * 4 * 2048 * (4 * j.K - 3) *
+                      (sh * (nblk + dv - 1) + 4 * dv * nblk))
     ws = torch.empty(F.batch_workspace_size(len(descs)), dtype=torch.uint8, device=dev)
 
     def run_batch():

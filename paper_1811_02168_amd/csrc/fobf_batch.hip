@@ -14,8 +14,12 @@
 // One launch serves all jobs of one precision whose radius class fits the
 // kernel: DV = ceil((16 + 2r) / 16) <= 4 (r <= 24), DV = 5 (r <= 32) or
 // 6 <= DV <= 7 (r <= 48).
-// The float32 body runs with 4*DV horizontal steps (Toeplitz slices past
-// the band are zero), so one instantiation covers a whole radius class.
+// The float32 body is the single-image kernel's tile body for the job's own
+// step count (every SH of the class is instantiated), so a float32 batch
+// image equals its single-image launch bit for bit; measured on the
+// 256-image batch of uneven sizes and radii 6..24 this is also 5% faster
+// than one body per class with its steps rounded up to 4 DV (9.7 vs
+// 10.25 ms).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -99,21 +103,26 @@ __global__ __launch_bounds__(MTHREADS, batch_min_blocks<DVHI>()) void batch_kern
       float* Bt = lds + LDS_TABLE;
       float* At = Bt + 4 * DVHI * 64;
       float* nd = At + 4 * DVHI * 64;
-      switch (dv) {
-#define FOBF_F32_CASE(D)                                              \
-  case D:                                                             \
-    if constexpr (D >= DVLO && D <= DVHI) {                           \
-      build_f32_tables<4 * D>(im, tbl, im.r, Bt, At);                 \
-      __syncthreads();                                                \
-      f32_tile<4 * D>(im, tx, ty, nblk, tbl, Bt, At, nd);             \
-    }                                                                 \
+      // the job's own step count SH = ceil((16 + 2r) / 4): the tile body
+      // of the single-image kernel, bit for bit
+      switch ((MSTRIP + 2 * im.r + 3) / 4) {
+#define FOBF_F32_CASE(S)                                                  \
+  case S:                                                                 \
+    if constexpr ((S + 3) / 4 >= DVLO && (S + 3) / 4 <= DVHI) {           \
+      build_f32_tables<S>(im, tbl, im.r, Bt, At);                         \
+      __syncthreads();                                                    \
+      f32_tile<S>(im, tx, ty, nblk, tbl, Bt, At, nd);                     \
+    }                                                                     \
     break;
-        FOBF_F32_CASE(2)
-        FOBF_F32_CASE(3)
-        FOBF_F32_CASE(4)
-        FOBF_F32_CASE(5)
-        FOBF_F32_CASE(6)
-        FOBF_F32_CASE(7)
+#define FOBF_F32_CASES(D) \
+  FOBF_F32_CASE(4 * D - 3) FOBF_F32_CASE(4 * D - 2) FOBF_F32_CASE(4 * D - 1) FOBF_F32_CASE(4 * D)
+        FOBF_F32_CASES(2)
+        FOBF_F32_CASES(3)
+        FOBF_F32_CASES(4)
+        FOBF_F32_CASES(5)
+        FOBF_F32_CASES(6)
+        FOBF_F32_CASES(7)
+#undef FOBF_F32_CASES
 #undef FOBF_F32_CASE
         default: break;
       }
