@@ -122,6 +122,16 @@ def write_trace_summary(stats_csv, bench_json):
     line = json.loads(open(bench_json).read().strip().splitlines()[-1])
     flop = line["roofline"]["flop_per_px"] * line["config"]["H"] * line["config"]["W"]
     rows = list(csv.DictReader(open(stats_csv)))
+    # per-dispatch durations, in dispatch order, from the trace beside the
+    # stats: the last steps x images launches of each kernel are the
+    # bench's timed region (the others are its warm-up and tuning runs)
+    durs = {}
+    trace_csv = os.path.join(os.path.dirname(stats_csv), "fobf_kernel_trace.csv")
+    if os.path.exists(trace_csv):
+        for t in sorted(csv.DictReader(open(trace_csv)), key=lambda t: int(t["Dispatch_Id"])):
+            durs.setdefault(t["Kernel_Name"], []).append(
+                int(t["End_Timestamp"]) - int(t["Start_Timestamp"]))
+    n_timed = line["steps"] * line["config"]["images_per_step"]
     out = ["# Kernel trace: 4096^2 image, theta = 10 (61 taps), K = 8, "
            "sigma in {20, 50, 100}", "",
            "Command (from the repository root on the MI355X host; "
@@ -132,20 +142,29 @@ def write_trace_summary(stats_csv, bench_json):
            "--no-cpu-baseline --no-serve --no-batch", "",
            "Summary written by `python3 bench.py --write-trace-summary "
            "<out>/trace/fobf_kernel_stats.csv <bench JSON line>`.", "",
-           "| Kernel | Calls | Average ns | Min ns | Max ns | TFLOP/s (7076 flop/px) "
-           "| peak of its products (TFLOP/s) | fraction of that peak |",
-           "|---|---|---|---|---|---|---|---|"]
+           f"Averages over all calls (warm-up and tuning runs included) and over the "
+           f"last {n_timed} calls of each kernel, the bench's timed region "
+           f"({line['steps']} steps x {line['config']['images_per_step']} images); "
+           "the rate and fraction use the timed-region average.", "",
+           "| Kernel | Calls | Average ns | Min ns | Max ns | timed-region average ns "
+           "| TFLOP/s (7076 flop/px) | peak of its products (TFLOP/s) | fraction of that peak |",
+           "|---|---|---|---|---|---|---|---|---|"]
     for key, subs in TRAFFIC_KERNELS.items():
         for r in rows:
             if any(x in r["Name"] for x in subs):
                 avg = float(r["AverageNs"])
-                tf = flop / (avg * 1e-9) / 1e12
+                d = durs.get(r["Name"], [])[-n_timed:]
+                tavg = sum(d) / len(d) if d else avg
+                tf = flop / (tavg * 1e-9) / 1e12
                 pk = KERNEL_PEAK.get(key, 2500.0)
                 out.append(f"| `{r['Name'][:90]}` {KERNEL_LABELS[key]} | {r['Calls']} | "
                            f"{avg:,.0f} | {int(float(r['MinNs'])):,} | "
-                           f"{int(float(r['MaxNs'])):,} | {tf:.1f} | {pk:g} | "
+                           f"{int(float(r['MaxNs'])):,} | {tavg:,.0f} | {tf:.1f} | {pk:g} | "
                            f"{tf / pk:.3f} |")
-    out += ["", "HIP-event timing inside the same traced run (`roofline.kernel_ms` "
+    out += ["", f"The traced run's own step: {line['ms_per_step']} ms for "
+            f"{line['config']['images_per_step']} images (driver-side wall clock of the "
+            "timed steps).", "",
+            "HIP-event timing inside the same traced run (`roofline.kernel_ms` "
             f"of its JSON line): headline fp32 {line['roofline']['kernel_ms']} ms per launch; "
             + ", ".join(f"{k} {v['kernel_ms']} ms" for k, v in line.get("mixed", {}).items())
             + ".", ""]
