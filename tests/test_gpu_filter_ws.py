@@ -81,6 +81,7 @@ SHAPES = [
     (2600, 3000, 7.0, 8, 25.0, 1),     # r = 21, DV = 4
     (4100, 2049, 10.0, 8, 50.0, 2),    # r = 30, DV = 5
     (3001, 1500, 12.0, 5, 60.0, 0),    # r = 36, DV = 6
+    (2048, 2300, 4.0, 32, 12.0, 1),    # r = 12, DV = 3, the largest order
 ]
 
 
@@ -216,7 +217,7 @@ def test_ws_fp32_bitwise_random():
     assert used >= 12
 
 
-@pytest.mark.parametrize("K", [1, 2, 3, 4, 7])
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 7, 16, 32])
 def test_ws_fp16_every_group_shape(K):
     """The fp16 workspace form folds channel groups two frequencies at a
     time ({f, 1}, {2, 3}, .., a last single frequency when K is even, {f}
