@@ -256,16 +256,17 @@ int fobf_effective_prec(int prec, int K, int T, const double* c);
  * FOBF_FP32 stage each block's channels once per workgroup instead of once
  * per wave (its output is then identical to fobf_filter's, bit for bit).
  * Every precision uses it for images tall enough to give such tiles while
- * still filling the device (e.g. 2048^2 and larger at theta <= 13.5); there
- * FOBF_FP16_STAGE also folds two frequencies per pass over the tile (N and
- * D make half the round trips; same output as one at a time).  For every
- * other case the workspace is not used and fobf_filter_ws behaves exactly
- * as fobf_filter.
+ * still filling the device (e.g. 2048^2 and larger at theta <= 13.5),
+ * FOBF_FP32 only from radius 14 on (theta > 13/3: below, the N/D round
+ * trips cost more than they save); there FOBF_FP16_STAGE also folds two
+ * frequencies per pass over the tile (N and D make half the round trips;
+ * same output as one at a time).  For every other case the workspace is not
+ * used and fobf_filter_ws behaves exactly as fobf_filter.
  *
  * fobf_filter_workspace_size: *bytes = the workspace fobf_filter_ws needs
  *   for an H x W image at this theta and precision (0: none; about 8 bytes
- *   per pixel otherwise, the same for every precision).  Host-only, no
- *   device work.
+ *   per pixel otherwise, the same for every precision that uses it).
+ *   Host-only, no device work.
  *   Validates H, W >= 0, theta, prec and bytes != NULL (FOBF_EINVAL).
  * fobf_filter_ws: arguments as fobf_filter, plus d_work (device memory, 4-
  *   byte aligned, overlapping neither image) of work_bytes >=

