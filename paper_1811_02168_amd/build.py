@@ -29,6 +29,7 @@ SOURCES = [
     "fobf_mfma_ws.hip",
     "fobf_static.hip",
     "fobf_batch.hip",
+    "fobf_batch_staged.hip",
     "fobf_tune.hip",
     "fobf_serve.cpp",
     "fobf_peak.hip",
