@@ -33,7 +33,12 @@
 //   type (shared by all its strips) -- one fp16 word, or hi + lo words of
 //   bf16 or fp16 -- horizontal results are rounded the same way for the
 //   vertical product; N and D live in LDS.
-// In both, channel f (k = 0) forms a group of its own without trig, and
+// workspace forms (every precision): N and D of each tile live in a device
+//   workspace instead, which frees the LDS for 512-row tiles; float32 then
+//   stages its channels once per workgroup too (float32 words, the same
+//   sums in the same order as the per-lane path).
+// In all of them channel f (k = 0) forms a group of its own without trig
+// (merged with frequency 1 in the float32 and fp16 workspace forms), and
 // every k >= 1 forms a group of four channels sharing one sin/cos.
 
 
