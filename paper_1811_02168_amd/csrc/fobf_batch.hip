@@ -90,6 +90,38 @@ fobf_status filter_batch_impl(const fobf_job* jobs, int n, void* d_work, size_t 
     e.cls = prec * kRadiusClasses + radius_class(e.b.dv);
     es.push_back(e);
   }
+  // a launch class with only a few tiles per workgroup slot runs them in a
+  // few rounds, each as long as the longest tile's chain of blocks: cap the
+  // tile height of all its jobs where that shortens rounds x chain (the
+  // short requests of a serving batch; large batches keep their heights)
+  for (int cls = 0; cls < MAX_LAUNCHES; ++cls) {
+    const long slots = static_cast<long>(device_cus()) *
+                       (cls % kRadiusClasses == 2 ? 1 : 2);
+    int dvmax = 0;
+    auto tiles = [&](int cap) {
+      long t = 0;
+      for (const Entry& e : es)
+        if (e.cls == cls) {
+          const int nb = std::min(e.b.nblk, cap);
+          t += static_cast<long>(e.b.ntx) * ((e.b.p.H + 16 * nb - 1) / (16 * nb));
+          dvmax = std::max(dvmax, e.b.dv);
+        }
+      return t;
+    };
+    const long t8 = tiles(BATCH_NBLK_MAX);
+    if (t8 == 0 || t8 >= 4 * slots) continue;
+    auto cost = [&](int cap) { return ((tiles(cap) + slots - 1) / slots) * (cap + dvmax - 1); };
+    int cap = BATCH_NBLK_MAX;
+    long best = cost(cap);
+    for (int c = BATCH_NBLK_MAX - 1; c >= 1; --c)
+      if (cost(c) < best) best = cost(c), cap = c;
+    for (Entry& e : es)
+      if (e.cls == cls && e.b.nblk > cap) {
+        e.b.nblk = cap;
+        e.b.nty = (e.b.p.H + 16 * cap - 1) / (16 * cap);
+        e.cost = static_cast<double>(4 * e.b.p.K - 3) * (cap + e.b.dv - 1) * (2 * e.b.p.r + 1);
+      }
+  }
   // per class: largest tiles first (their tail is the hardest to hide)
   std::stable_sort(es.begin(), es.end(), [](const Entry& a, const Entry& b) {
     if (a.cls != b.cls) return a.cls < b.cls;

@@ -60,6 +60,7 @@ fobf_status launch_f32_sh(const ImageParams& p, int nblk, void* stream) {
   constexpr int DV = (SH + 3) / 4;
   static const bool once = (allow_big_lds(mfma_f32_kernel<SH>), true);
   (void)once;
+  nblk = fill_nblk(p.H, p.W, nblk, MWAVES, SH <= 20 ? 2 : 1, DV);
   const size_t lds = sizeof(float) * (LDS_TABLE + 8 * DV * 64 +
                                       static_cast<size_t>(MWAVES) * 2 * nblk * 256);
   dim3 grid(padded_blocks(p, nblk));
@@ -87,7 +88,7 @@ fobf_status launch_staged_dv(const ImageParams& p, int nblk, void* stream) {
   // the tallest tile whose per-wave N and D still fit next to the staging
   constexpr size_t fixed = sizeof(float) * LDS_TABLE + staged_buf_bytes<OT, DV, NW>();
   constexpr int cap = static_cast<int>((160 * 1024 - fixed) / (sizeof(float) * NW * 2 * 256));
-  nblk = std::min(nblk, cap);
+  nblk = fill_nblk(p.H, p.W, std::min(nblk, cap), NW, 1, DV);
   const size_t lds = fixed + sizeof(float) * NW * 2 * nblk * 256;
   dim3 grid(padded_blocks(p, nblk, NW));
   ImageParams q = p;

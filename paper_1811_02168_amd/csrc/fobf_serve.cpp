@@ -5,7 +5,9 @@
 // requests in arrival order while the number in flight and their device
 // bytes (below) fit the configured limits, merges up to
 // max_batch admitted requests into one batch, and issues the batch on the
-// next of a few HIP streams ("lanes"): per request a stream-ordered device
+// least loaded of a few HIP streams ("lanes": the one with the fewest
+// pixels in flight, so that a small request does not wait in stream order
+// behind a large one): per request a stream-ordered device
 // allocation and the host-to-device copy, then ONE persistent batched
 // launch for all of them (fobf_filter_batch's kernel), then the copies back
 // and stream-ordered frees.  A request large enough for the workspace form
@@ -115,7 +117,10 @@ struct fobf_server {
   std::condition_variable cv_fit;
   std::deque<CoefKey> fit_queue;
   hipStream_t lanes[kLanes] = {};
-  int next_lane = 0;
+  // pixels of the batches issued on each lane and not yet done (guarded
+  // by mu): a new batch goes to the lane with the least outstanding work,
+  // so that small requests do not queue behind a large one in stream order
+  double lane_pixels[kLanes] = {};
   // fit cache: (R, sigma bits, K) -> (state, T, c, device row).  Guarded
   // by mu; only the scheduler thread uploads rows.
   enum CoefState { kFitting, kReady, kFailed };
@@ -140,6 +145,8 @@ namespace {
 struct Batch {
   fobf_server* s;
   std::vector<Req*> reqs;
+  int lane;
+  double pixels;   // the batch's share of lane_pixels[lane]
 };
 
 // Runs on a HIP runtime thread when a batch's stream reaches its end: no
@@ -160,6 +167,7 @@ void batch_done(void* arg) {
       if (q->res.status != FOBF_OK) s->stats.failed += 1;
     }
     s->batches_running -= 1;
+    s->lane_pixels[b->lane] -= b->pixels;
   }
   s->cv_done.notify_all();
   s->cv_work.notify_all();
@@ -323,8 +331,14 @@ void fitter_main(fobf_server* s) {
 }
 
 void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
-  const int lane = s->next_lane;
-  s->next_lane = (s->next_lane + 1) % kLanes;
+  // the lane with the least outstanding work (the copies, which dominate a
+  // request's device time, scale with its pixels); only this thread issues
+  int lane = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int i = 1; i < kLanes; ++i)
+      if (s->lane_pixels[i] < s->lane_pixels[lane]) lane = i;
+  }
   hipStream_t st = s->lanes[lane];
   bool inject = false;
   {
@@ -446,9 +460,12 @@ void submit_batch(fobf_server* s, std::vector<Req*>& adm) {
     hipFreeAsync(q->d_out, st);
   }
   if (ws) hipFreeAsync(ws, st);
-  Batch* b = new Batch{s, ok};
+  double pixels = 0.0;
+  for (Req* q : ok) pixels += static_cast<double>(q->r.H) * q->r.W;
+  Batch* b = new Batch{s, ok, lane, pixels};
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    s->lane_pixels[lane] += pixels;
     s->batches_running += 1;
     s->stats.batches += 1;
     s->stats.coef_entries = s->coef_used;

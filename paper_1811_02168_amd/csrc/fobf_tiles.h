@@ -45,6 +45,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "fobf_internal.h"
 
 #ifndef FOBF_CHECKS
@@ -1610,6 +1612,42 @@ inline unsigned padded_blocks(const ImageParams& p, int nblk, int nw = MWAVES) {
   const long ntx = (p.W + nw * MSTRIP - 1) / (nw * MSTRIP);
   const long nty = (p.H + 16 * nblk - 1) / (16 * nblk);
   return static_cast<unsigned>(((ntx * nty + 7) / 8) * 8);
+}
+
+// Compute units of the current device, looked up once per device.
+inline int device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int n = cache[dev].load(std::memory_order_relaxed);
+  if (n == 0) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cache[dev].store(n, std::memory_order_relaxed);
+  }
+  return n;
+}
+
+// Tile height (at most the tuned nblk) for an image with only a few tiles
+// per workgroup slot (per_cu resident workgroups of nw strips per CU):
+// there the tiles run in a few rounds of one per slot, each round as long
+// as one tile's chain of nblk + DV - 1 blocks, so the height that
+// minimises rounds x chain wins even though shorter tiles recompute more
+// halo rows (128^2 .. 1024^2 images: 2-3x faster).  Images with many
+// rounds keep the tuned height.
+inline int fill_nblk(int H, int W, int nblk, int nw, int per_cu, int dv) {
+  const long ntx = (W + nw * MSTRIP - 1) / (nw * MSTRIP);
+  const long slots = static_cast<long>(device_cus()) * per_cu;
+  auto tiles = [&](int n) { return ntx * ((H + 16L * n - 1) / (16L * n)); };
+  if (tiles(nblk) >= 4 * slots) return nblk;
+  int best = nblk;
+  long best_cost = ((tiles(nblk) + slots - 1) / slots) * (nblk + dv - 1);
+  for (int n = nblk - 1; n >= 1; --n) {
+    const long cost = ((tiles(n) + slots - 1) / slots) * (n + dv - 1);
+    if (cost < best_cost) best = n, best_cost = cost;
+  }
+  return best;
 }
 
 inline fobf_status check_launch(const char* what) {
