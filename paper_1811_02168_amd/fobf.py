@@ -161,6 +161,18 @@ def _load(path=LIB_PATH):
     return lib
 
 
+# libfobf.so links the system ROCm's HIP runtime; PyTorch brings its own
+# copy.  Both work in one process when PyTorch's is started first (the
+# order every test and the benchmark use); started the other way round,
+# PyTorch may find no device.  So PyTorch, where present, is started here,
+# before the library is loaded.
+try:
+    import torch as _torch
+    if _torch.cuda.is_available():
+        _torch.cuda.init()
+except ImportError:   # the C ABI needs no PyTorch
+    pass
+
 lib = _load()
 
 
