@@ -353,6 +353,11 @@ fobf_status fobf_filter_batch(const fobf_job* jobs, int n, void* d_work,
  * of order K on the device (it allocates two temporary H x W buffers and
  * synchronises `hip_stream`) and records the fastest; until then built-in
  * defaults apply.  The table can be saved to and loaded from a text file.
+ * The table's height is an upper bound: an image (or a batch launch class)
+ * with fewer than four rounds of tiles per workgroup slot of the device
+ * runs shorter tiles where that shortens rounds x tile chain (small images
+ * are latency-bound, not throughput-bound).  Tune on images of the size
+ * the table is meant for (2048^2 and up fill the device at the default).
  * ---------------------------------------------------------------------- */
 fobf_status fobf_autotune(int prec, int H, int W, int K, void* hip_stream);
 fobf_status fobf_tune_save(const char* path);
