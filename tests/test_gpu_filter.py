@@ -226,6 +226,52 @@ def test_c2_full_size_sampled(algo, prec):
         assert np.all(np.isfinite(got))
 
 
+# images with few tiles per workgroup slot, which run shorter tiles than
+# the tuned height (ragged, non-square, every radius class)
+SHORT_TILE_SHAPES = [(724, 724, 6.0, 6, 40.0), (1500, 1100, 10.0, 8, 50.0),
+                     (300, 2500, 3.0, 4, 25.0), (1024, 1024, 13.0, 5, 70.0),
+                     (97, 3001, 16.0, 3, 30.0)]
+
+
+@pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
+def test_short_tile_shapes_against_eq1(algo, prec):
+    """Sampled outputs against eq. (1) with the fitted cosine series on
+    images that take the small-image tile heights."""
+    for i, (H, W, theta, K, sigma) in enumerate(SHORT_TILE_SHAPES):
+        f = workloads.voronoi_image(H, W, max(4, H * W // 20000), True, 600 + i)
+        T, c = fitted(sigma, K)
+        got = gpu_filter(f, theta, K, T, c, prec=prec, algo=algo, pad=i)
+        ys, xs = sample_points(H, W, 300, 11 + i)
+        ref, num, den = O.brute_bf_points(f, theta, O.cosine_series(c, T), ys, xs)
+        mask = den / O.blur_weight(H, W, theta)[ys, xs] >= DMASK
+        err = float(np.abs(got[ys, xs] - ref)[mask].max())
+        print("short tiles", algo, prec, H, W, theta, err)
+        assert err <= tol(prec), (H, W, theta, err)
+        assert np.all(np.isfinite(got))
+
+
+def test_short_tile_fp32_equals_batch_launch():
+    """float32 sums do not depend on the tile height: the single launch
+    (small-image tile heights) and the batch launch (its own class cap) of
+    each image agree bit for bit."""
+    import torch
+    import paper_1811_02168_amd as F
+    imgs, outs, jobs = [], [], []
+    for i, (H, W, theta, K, sigma) in enumerate(SHORT_TILE_SHAPES):
+        f = workloads.voronoi_image(H, W, 30, True, 700 + i)
+        T, c = fitted(sigma, K)
+        img = torch.from_numpy(f.astype(np.float32)).cuda()
+        out = torch.full_like(img, -1.0)
+        imgs.append((img, theta, K, T, c))
+        outs.append(out)
+        jobs.append(F.make_job(img, out, theta, K, T, c))
+    F.filter_batch(jobs)
+    for (img, theta, K, T, c), out in zip(imgs, outs):
+        single = F.filter(img, theta, K, T, c, algo="mfma")
+        torch.cuda.synchronize()
+        assert torch.equal(single, out), (img.shape, theta)
+
+
 @pytest.mark.parametrize("algo,prec", MODES, ids=MODE_IDS)
 def test_c3_full_size_symmetries(algo, prec):
     """4096^2, theta=10, K=8, sigma=50, every output pixel: the filter
