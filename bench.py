@@ -539,6 +539,14 @@ def main():
         accuracy = accuracy_leg(img, cfg, modes, refs, F, torch)
         refs = None
 
+    small = None
+    if not args.no_mixed:
+        try:
+            small = small_configs_leg(F, torch)
+        except Exception as e:  # reported, never hidden
+            small = {"error": repr(e)}
+        print(f"[bench] small configs: {small}", file=sys.stderr, flush=True)
+
     batch = None
     if not args.no_batch:
         try:
@@ -585,10 +593,44 @@ def main():
         "mixed": mixed,
         "accuracy_vs_fp64_oracle": accuracy,
         "host_fit": host_fit,
+        "small_configs": small,
         "batch": batch,
         "serving": serving,
     }
     print(json.dumps(line))
+
+
+def small_configs_leg(F, torch):
+    """The two smaller parity workloads (256^2, theta = 3, K = 4; 1024^2,
+    theta = 5, K = 6) through fobf_filter, fp32 and fp16 staging, resident
+    inputs: per-image kernel time by HIP events over repeated launches on
+    the current stream (context beside the paper's 256^2 timings)."""
+    import workloads
+    out = {}
+    st = torch.cuda.current_stream()
+    for cfg in (workloads.C1, workloads.C2):
+        img = torch.from_numpy(cfg.image().astype("float32")).cuda()
+        o = torch.empty_like(img)
+        rec = {"H": cfg.H, "W": cfg.W, "theta": cfg.theta, "K": cfg.K}
+        for prec in ("fp32", "fp16"):
+            ms = []
+            for sigma in cfg.sigmas:
+                co = F.fit(255, sigma, cfg.K, eps=cfg.eps)
+                call = lambda: F.filter(img, cfg.theta, cfg.K, co.T, co.c, prec=prec, out=o)
+                for _ in range(10):
+                    call()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                for _ in range(50):
+                    call()
+                e1.record(st)
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1) / 50)
+            avg = sum(ms) / len(ms)
+            rec[prec] = {"kernel_ms": round(avg, 4),
+                         "mpix_s": round(cfg.H * cfg.W / (avg * 1e-3) / 1e6, 1)}
+        out[cfg.name] = rec
+    return out
 
 
 def batch_leg(F, torch, n):
