@@ -182,8 +182,8 @@ __device__ __forceinline__ void chk_vtap(const Img& im, float w, int h, int m) {
 }
 
 // The float32 Toeplitz slices as every reader indexes them (lane's Bt[s]
-// for window column SH (lane/16) + s, At[4d + v] for ring row 16 d + 4
-// (lane/16) + v, against output column / row lane%16): in the LDS, and
+// for window column SH (lane/16) + s, At[4d + v] for ring row 16 d + 4 v
+// + lane/16, against output column / row lane%16): in the LDS, and
 // non-zero only inside the windows.  Once per channel group: the readers
 // index them the same way for every block.
 template <int SH>
@@ -197,7 +197,9 @@ __device__ __forceinline__ void chk_f32_tables(const Img& im, const float* Bt, c
     chk_lds(im, Bt + s * 64 + lane, 4);
     chk_lds(im, At + s * 64 + lane, 4);
     if (s < SH) chk_htap(im, Bt[s * 64 + lane], SH * lk + s, li);
-    chk_vtap(im, At[s * 64 + lane], 16 * (s >> 2) + 4 * lk + (s & 3), li);
+    chk_vtap(im, At[s * 64 + lane], 4 * s + lk, li);
+    // the vertical steps skipped (s >= SH) must carry only zero taps
+    FOBF_CHK(im, s < SH || At[s * 64 + lane] == 0.f, FOBF_CHECK_HALO_V);
   }
 #endif
 }
@@ -249,6 +251,16 @@ __device__ __forceinline__ void poison_lds(const Img& im, int from_bytes = 0) {
 // float32: 16x16x4 MFMA, channels on the fly, N/D in LDS
 // =========================================================================
 
+// Block row whose channels lane li feeds to the horizontal product (its A
+// row li): rows 4 (li % 4) + li / 4, a transposition of the 4 x 4 row
+// index.  The product's result register v of lane l (result row 4 (l/16)
+// + v) then holds block row 4 v + l/16, so the vertical step that takes
+// register v contracts the four consecutive rows 4v .. 4v + 3 of a block
+// instead of rows v, v + 4, v + 8, v + 12.  Vertical step j = 4 d + v then
+// meets non-zero taps only while 4 j <= 15 + 2r, i.e. for j < SH: the
+// steps from SH to 4 DV - 1 (all-zero Toeplitz slices) are skipped.
+__device__ __forceinline__ int hrow_of_lane(int li) { return 4 * (li & 3) + (li >> 2); }
+
 // One channel group over this wave's strip: G = 1 is {f} (k = 0, no trig),
 // G = 4 is {C f, S f, C, S} of frequency k >= 1.  Bt / At are the
 // horizontal / vertical Toeplitz slices, one float per lane per MFMA step,
@@ -283,6 +295,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
   const int r = im.r;
   const int li = lane & 15;
   const int lk = lane >> 4;
+  const int hr = hrow_of_lane(li);   // block row of this lane's A operand
   const float kinv = static_cast<float>(k) * im.inv_period;
   const float ck = cS[k];
   const int QB = nblk + DV - 1;
@@ -290,17 +303,17 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
   const int gxo = min(x0w + li, im.W - 1);
   const size_t ld = static_cast<size_t>(im.ld_in);
 
-  // address of (row y0 - r + 16 q + li, column colbase) -- interior only
-  auto rowptr = [&](int q) { return im.in + (y0 - r + 16 * q + li) * ld + colbase; };
+  // address of (row y0 - r + 16 q + hr, column colbase) -- interior only
+  auto rowptr = [&](int q) { return im.in + (y0 - r + 16 * q + hr) * ld + colbase; };
   auto load_block = [&](int q, float (&v)[SH]) {
     if (!EDGE) {
       const float* p = rowptr(q);
-      chk_img(im, y0 - r + 16 * q + li, colbase);
-      chk_img(im, y0 - r + 16 * q + li, colbase + SH - 1);
+      chk_img(im, y0 - r + 16 * q + hr, colbase);
+      chk_img(im, y0 - r + 16 * q + hr, colbase + SH - 1);
 #pragma unroll
       for (int s = 0; s < SH; ++s) v[s] = p[s];
     } else {
-      const int row = y0 - r + 16 * q + li;
+      const int row = y0 - r + 16 * q + hr;
       const float* rp = im.in + static_cast<size_t>(min(max(row, 0), im.H - 1)) * ld;
 #pragma unroll
       for (int s = 0; s < SH; ++s) v[s] = rp[min(max(colbase + s, 0), im.W - 1)];
@@ -335,7 +348,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
         }
         // next block's row (the last block reloads its own row: branch-free)
         const int qn = (q + 1 < QB) ? q + 1 : q;
-        const int rown = y0 - r + 16 * qn + li;
+        const int rown = y0 - r + 16 * qn + hr;
         const float* pn = EDGE ? im.in + static_cast<size_t>(min(max(rown, 0), im.H - 1)) * ld
                                : rowptr(qn);
         if (!EDGE) {
@@ -343,7 +356,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
           chk_img(im, rown, colbase + SH - 1);
         }
         // ---- horizontal pass, H rows 16q .. 16q+15 of the strip ----
-        const int row = y0 - r + 16 * q + li;
+        const int row = y0 - r + 16 * q + hr;
         const bool rin = !EDGE || static_cast<unsigned>(row) < static_cast<unsigned>(im.H);
         f4 acc[G];
 #pragma unroll
@@ -390,6 +403,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
             tags.check(im, slot, pb + d);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
+              if (4 * d + v >= SH) break;   // all-zero slices
               const float av = At[(d * 4 + v) * 64 + lane];
 #pragma unroll
               for (int g = 0; g < G; ++g)
@@ -484,8 +498,9 @@ __device__ __forceinline__ void store_nd(const Img& im, int x0w, int y0, int nbl
 
 // Toeplitz slices as per-lane LDS tables: Bt[s][lane] (horizontal step s,
 // window column SH*(lane/16) + s against output column lane%16; 4*DV
-// entries, those beyond SH unused) and At[d*4+v][lane] (vertical, DV blocks
-// x 4 rows).
+// entries, those beyond SH unused) and At[j][lane] (vertical step j = 4d +
+// v: ring block d, rows 4v + lane/16, see hrow_of_lane; 4*DV entries, those
+// from SH on all zero and skipped).
 template <int SH>
 __device__ __forceinline__ void build_f32_tables(const Img& im, const float* gS, int r, float* Bt,
                                                  float* At) {
@@ -495,8 +510,7 @@ __device__ __forceinline__ void build_f32_tables(const Img& im, const float* gS,
     chk_lds(im, Bt + i, 4);
     chk_lds(im, At + i, 4);
     Bt[i] = tap(gS, SH * (l >> 4) + s - r - (l & 15), r);
-    const int d = s >> 2, v = s & 3;
-    At[i] = tap(gS, 16 * d + 4 * (l >> 4) + v - r - (l & 15), r);
+    At[i] = tap(gS, 4 * s + (l >> 4) - r - (l & 15), r);
   }
 }
 
@@ -972,7 +986,7 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
         stage_fetch<IW>(im, x0, rown, CWn, block_interior(rown), fvs);
         __syncthreads();
         // ---- horizontal pass of this wave's strip, from LDS ----
-        const float* arow = buf + li * PC + 16 * wave + SH * lk;
+        const float* arow = buf + hrow_of_lane(li) * PC + 16 * wave + SH * lk;
         // Pinned row pointers halve the kernel's vector adds; measured at
         // 4096^2 they gain 0.8-1.9% where SH is not a multiple of 4 (theta
         // = 6, 7, 10, 12) and lose 0.5-0.8% where it is (theta = 8, 5).
@@ -1007,6 +1021,7 @@ __device__ __forceinline__ void f32s_group(const Img& im, int k, int x0, int y0,
             tags.check(im, slot, pb + d);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
+              if (4 * d + v >= SH) break;   // all-zero slices
               const float av = TREG ? atr[d * 4 + v] : At[(d * 4 + v) * 64 + lane];
 #pragma unroll
               for (int g = 0; g < G; ++g)
