@@ -666,10 +666,10 @@ def batch_leg(F, torch, n):
                for j in jobs)
     # matrix-core flops the fp32 batch body executes: per tile of 4 strips x
     # nblk blocks and per channel, (nblk + DV - 1) horizontal 16-row blocks
-    # of SH = ceil((16 + 2r) / 4) steps and nblk vertical blocks of 4 DV
-    # steps, each step a 16x16x4 product (2048 flop); at small radii the
-    # 16-column band of the Toeplitz products is mostly zero taps (r = 6:
-    # 28 columns and 32 rows for 13 taps)
+    # and nblk vertical blocks, each of SH = ceil((16 + 2r) / 4) steps, a
+    # step a 16x16x4 product (2048 flop); at small radii the 16-wide band
+    # of the Toeplitz products is mostly zero taps (r = 6: 28 columns and
+    # 28 rows for 13 taps)
     exec_flop = 0
     for j in jobs:
         r = math.ceil(3 * j.theta)
@@ -679,7 +679,7 @@ def batch_leg(F, torch, n):
         nblk = max(1, min(nblk, 8, (j.H + 15) // 16))
         ntx, nty = -(-j.W // 64), -(-j.H // (16 * nblk))
         exec_flop += (ntx * nty * 4 * 2048 * (4 * j.K - 3) *
-                      (sh * (nblk + dv - 1) + 4 * dv * nblk))
+                      (sh * (nblk + dv - 1) + sh * nblk))
     ws = torch.empty(F.batch_workspace_size(len(descs)), dtype=torch.uint8, device=dev)
 
     def run_batch():
