@@ -284,6 +284,34 @@ def test_convergence_and_prop1_bound():
     assert errs[-1] > 90.0
 
 
+def test_prop1_bound_nearly_attained():
+    """The restated Proposition 1 bound is tight, not merely an upper bound:
+    a pixel at 0 whose whole window sits at R meets every neighbour at the
+    far end of the kernel's domain, where the fitted series' error is
+    largest (|phi_hat(R) - phi(R)| = delta for these fits), and all of that
+    error pulls the output one way.  The error there reaches over 3/4 of
+    the bound, so a bound with a looser constant (by 4/3 or more) fails."""
+    R = 255
+    theta = 1.0
+    rr = int(math.ceil(3 * theta))
+    n = 2 * rr + 1
+    f = np.full((n, n), float(R))
+    f[rr, rr] = 0.0
+    Wi = O.blur_weight(n, n, theta)
+    for sigma, K in ((40.0, 8), (60.0, 5)):
+        r = O.fit(R, sigma, K)
+        t = np.arange(-R, R + 1)
+        nu = 2 * np.pi / (2 * r["T"] + 1)
+        phihat = sum(r["c"][k] * np.cos(nu * t * k) for k in range(K))
+        err_t = np.abs(phihat - O.gaussian_range(sigma)(t))
+        assert err_t[-1] == pytest.approx(r["delta"], rel=1e-9)   # worst at t = R
+        bf = O.brute_bf(f, theta, O.gaussian_range(sigma))
+        fo = O.fourier_direct(f, theta, K, r["T"], r["c"])
+        bound = O.prop1_bound(R, r["delta"], Wi)[rr, rr]
+        err = abs(fo[rr, rr] - bf[rr, rr])
+        assert np.isfinite(bound) and 0.75 * bound <= err <= bound, (sigma, K, err, bound)
+
+
 def test_psnr_definition():
     """Sec. III: PSNR = 10 log10(255^2 / MSE)."""
     a = np.zeros((4, 4))
