@@ -142,12 +142,14 @@ def write_trace_summary(stats_csv, bench_json):
            "--no-cpu-baseline --no-serve --no-batch", "",
            "Summary written by `python3 bench.py --write-trace-summary "
            "<out>/trace/fobf_kernel_stats.csv <bench JSON line>`.", "",
-           f"Averages over all calls (warm-up and tuning runs included) and over the "
-           f"last {n_timed} calls of each kernel, the bench's timed region "
-           f"({line['steps']} steps x {line['config']['images_per_step']} images); "
-           "the rate and fraction use the timed-region average.", "",
-           "| Kernel | Calls | Average ns | Min ns | Max ns | timed-region average ns "
-           "| TFLOP/s (7076 flop/px) | peak of its products (TFLOP/s) | fraction of that peak |",
+           f"Per kernel: the average over the last {n_timed} calls, the bench's timed "
+           f"region ({line['steps']} steps x {line['config']['images_per_step']} images), "
+           "which the rate and fraction use; then rocprofv3's statistics over all "
+           "calls (the warm-up and tuning runs included, slower first calls among "
+           "them).", "",
+           "| Kernel | timed-region average ns | TFLOP/s (7076 flop/px) "
+           "| peak of its products (TFLOP/s) | fraction of that peak | Calls "
+           "| all-calls average ns | Min ns | Max ns |",
            "|---|---|---|---|---|---|---|---|---|"]
     for key, subs in TRAFFIC_KERNELS.items():
         for r in rows:
@@ -157,10 +159,10 @@ def write_trace_summary(stats_csv, bench_json):
                 tavg = sum(d) / len(d) if d else avg
                 tf = flop / (tavg * 1e-9) / 1e12
                 pk = KERNEL_PEAK.get(key, 2500.0)
-                out.append(f"| `{r['Name'][:90]}` {KERNEL_LABELS[key]} | {r['Calls']} | "
+                out.append(f"| `{r['Name'][:90]}` {KERNEL_LABELS[key]} | {tavg:,.0f} | "
+                           f"{tf:.1f} | {pk:g} | {tf / pk:.3f} | {r['Calls']} | "
                            f"{avg:,.0f} | {int(float(r['MinNs'])):,} | "
-                           f"{int(float(r['MaxNs'])):,} | {tavg:,.0f} | {tf:.1f} | {pk:g} | "
-                           f"{tf / pk:.3f} |")
+                           f"{int(float(r['MaxNs'])):,} |")
     out += ["", f"The traced run's own step: {line['ms_per_step']} ms for "
             f"{line['config']['images_per_step']} images (driver-side wall clock of the "
             "timed steps).", "",
