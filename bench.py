@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--write-sq-summary", nargs=2, metavar=("PASS1_DIR", "PASS2_DIR"),
                     help="turn the two SQ counter passes of --profile-run (rocprofv3 "
                     "--pmc output directories) into profiles/fobf_c3_sq_counters.md, then exit")
+    ap.add_argument("--write-batch-trace-summary", nargs=2, metavar=("STATS_CSV", "BENCH_JSON"),
+                    help="turn a rocprofv3 --kernel-trace --stats summary of a "
+                    "bench run with the batch leg (and that run's JSON line) into "
+                    "profiles/fobf_c4_batch_trace.md, then exit")
     ap.add_argument("--write-trace-summary", nargs=2, metavar=("STATS_CSV", "BENCH_JSON"),
                     help="turn a rocprofv3 --kernel-trace --stats summary of a "
                     "bench run (and that run's JSON line) into "
@@ -171,6 +175,55 @@ def write_trace_summary(stats_csv, bench_json):
             + ", ".join(f"{k} {v['kernel_ms']} ms" for k, v in line.get("mixed", {}).items())
             + ".", ""]
     with open(os.path.join(ROOT, "profiles", "fobf_c3_kernel_trace.md"), "w") as fh:
+        fh.write("\n".join(out))
+
+
+def write_batch_trace_summary(stats_csv, bench_json):
+    """profiles/fobf_c4_batch_trace.md from `rocprofv3 --kernel-trace --stats`
+    of a bench run with the batch leg: the persistent batch kernels' device
+    time per launch beside the bench's wall-clock time per batch."""
+    import csv
+    line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    b = line["batch"]
+    rows = list(csv.DictReader(open(stats_csv)))
+    batch = [r for r in rows if "batch_kernel" in r["Name"]]
+    # per-dispatch durations in dispatch order: launches 2..6 of each batch
+    # kernel are the bench's 5 timed batches (the first is its untimed run)
+    durs = {}
+    trace_csv = os.path.join(os.path.dirname(stats_csv),
+                             os.path.basename(stats_csv).replace("kernel_stats", "kernel_trace"))
+    if os.path.exists(trace_csv):
+        for t in sorted(csv.DictReader(open(trace_csv)), key=lambda t: int(t["Dispatch_Id"])):
+            if "batch_kernel" in t["Kernel_Name"]:
+                durs.setdefault(t["Kernel_Name"], []).append(
+                    int(t["End_Timestamp"]) - int(t["Start_Timestamp"]))
+    out = ["# Kernel trace of the batch leg: 256 uneven images (C4), 168 Mpix", "",
+           "Command (from the repository root on the MI355X host; "
+           "`cd /tmp && export TMPDIR=/tmp` first):", "",
+           "    rocprofv3 --kernel-trace --stats -d <out>/c4 -o c4 --output-format csv -- \\",
+           "        python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-serve "
+           "--no-mixed", "",
+           "Summary written by `python3 bench.py --write-batch-trace-summary "
+           "<out>/c4/c4_kernel_stats.csv <bench JSON line>`.", "",
+           "The persistent batch launches one kernel per precision and radius class "
+           "(all of C4 is in the r <= 24 class); float32 runs 7 times (one untimed, "
+           "5 timed, one for the equality check), two-word fp16 6 times.", "",
+           "| Kernel | timed launches (2..6) average ns | Calls | all-calls average ns "
+           "| Min ns | Max ns |",
+           "|---|---|---|---|---|---|"]
+    for r in batch:
+        d = durs.get(r["Name"], [])[1:6]
+        tavg = f"{sum(d) / len(d):,.0f}" if d else "-"
+        out.append(f"| `{r['Name'][:110]}` | {tavg} | {r['Calls']} | "
+                   f"{float(r['AverageNs']):,.0f} | "
+                   f"{int(float(r['MinNs'])):,} | {int(float(r['MaxNs'])):,} |")
+    out += ["",
+            "The same run's bench line (wall clock per batch, host work included): "
+            f"persistent float32 {b['persistent']['ms']} ms, two-word fp16 "
+            f"{b['persistent_fp16x2']['ms']} ms, one launch per image "
+            f"{b['per_image']['ms']} ms; every float32 batch image equal to its "
+            f"single launch (max |difference| {b['max_abs_batch_vs_single']}).", ""]
+    with open(os.path.join(ROOT, "profiles", "fobf_c4_batch_trace.md"), "w") as fh:
         fh.write("\n".join(out))
 
 
@@ -380,6 +433,9 @@ def main():
         return
     if args.write_trace_summary:
         write_trace_summary(*args.write_trace_summary)
+        return
+    if args.write_batch_trace_summary:
+        write_batch_trace_summary(*args.write_batch_trace_summary)
         return
     if args.write_sq_summary:
         write_sq_summary(*args.write_sq_summary)
