@@ -65,6 +65,10 @@ def parse():
                     help="turn a rocprofv3 --kernel-trace --stats summary of a "
                     "bench run with the batch leg (and that run's JSON line) into "
                     "profiles/fobf_c4_batch_trace.md, then exit")
+    ap.add_argument("--write-serve-trace-summary", nargs=2, metavar=("TRACE_CSV", "BENCH_JSON"),
+                    help="turn a rocprofv3 --kernel-trace of a bench run with the "
+                    "serving leg (and that run's JSON line) into "
+                    "profiles/fobf_c5_serve_trace.md, then exit")
     ap.add_argument("--write-trace-summary", nargs=2, metavar=("STATS_CSV", "BENCH_JSON"),
                     help="turn a rocprofv3 --kernel-trace --stats summary of a "
                     "bench run (and that run's JSON line) into "
@@ -224,6 +228,57 @@ def write_batch_trace_summary(stats_csv, bench_json):
             f"{b['per_image']['ms']} ms; every float32 batch image equal to its "
             f"single launch (max |difference| {b['max_abs_batch_vs_single']}).", ""]
     with open(os.path.join(ROOT, "profiles", "fobf_c4_batch_trace.md"), "w") as fh:
+        fh.write("\n".join(out))
+
+
+def write_serve_trace_summary(trace_csv, bench_json):
+    """profiles/fobf_c5_serve_trace.md from `rocprofv3 --kernel-trace` of a
+    bench run with the serving leg only: the device time of the kernels the
+    server launched (from its first batch on), per kernel family, beside the
+    requests' end-to-end latencies of the same run."""
+    import csv
+    line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    sv = line["serving"]
+    ds = sorted(csv.DictReader(open(trace_csv)), key=lambda t: int(t["Dispatch_Id"]))
+    first = next((i for i, t in enumerate(ds) if "batch_kernel" in t["Kernel_Name"]), len(ds))
+    fam = {}
+    for t in ds[first:]:
+        n = t["Kernel_Name"]
+        key = ("persistent batch kernel" if "batch_kernel" in n else
+               "workspace form (tall requests)" if "_ws_kernel" in n else
+               "batch counter reset" if "reset_counter" in n else
+               "HIP runtime copy kernel (host-device copies it runs as a kernel)"
+               if "copyBuffer" in n else "other")
+        fam.setdefault(key, []).append((int(t["End_Timestamp"]) - int(t["Start_Timestamp"])) / 1e6)
+
+    def pct(v, q):
+        v = sorted(v)
+        return v[min(len(v) - 1, int(q * len(v)))]
+
+    out = ["# Kernel trace of the serving leg (C5: Poisson arrivals at 200 requests/s, "
+           "128^2..4096^2, half fp32 and half fp16-staged)", "",
+           "Command (from the repository root on the MI355X host; "
+           "`cd /tmp && export TMPDIR=/tmp` first):", "",
+           "    rocprofv3 --kernel-trace -d <out>/c5 -o c5 --output-format csv -- \\",
+           "        python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-batch "
+           "--no-mixed --serve-requests 1000", "",
+           "Summary written by `python3 bench.py --write-serve-trace-summary "
+           "<out>/c5/c5_kernel_trace.csv <bench JSON line>`.", "",
+           "Device time of every kernel the server launched (warm and cold legs "
+           "together), per kernel family:", "",
+           "| Kernel family | launches | total ms | mean ms | p50 ms | p99 ms | max ms |",
+           "|---|---|---|---|---|---|---|"]
+    for k, v in sorted(fam.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"| {k} | {len(v)} | {sum(v):.1f} | {sum(v) / len(v):.4f} | "
+                   f"{pct(v, 0.5):.4f} | {pct(v, 0.99):.4f} | {max(v):.4f} |")
+    w, c = sv["warm"], sv["cold"]
+    out += ["", "The same run's requests, end to end (submit to completion, PCIe copies "
+            f"included): warm cache p50 {w['p50_ms']} ms, p99 {w['p99_ms']} ms "
+            f"({w['requests']} timed); cold cache p50 {c['p50_ms']} ms, p99 {c['p99_ms']} ms "
+            f"({c['requests']}). Their device share (copy in, kernels, copy out) "
+            f"p50 {w['breakdown_ms']['device']['p50']} / p99 "
+            f"{w['breakdown_ms']['device']['p99']} ms (warm).", ""]
+    with open(os.path.join(ROOT, "profiles", "fobf_c5_serve_trace.md"), "w") as fh:
         fh.write("\n".join(out))
 
 
@@ -436,6 +491,9 @@ def main():
         return
     if args.write_batch_trace_summary:
         write_batch_trace_summary(*args.write_batch_trace_summary)
+        return
+    if args.write_serve_trace_summary:
+        write_serve_trace_summary(*args.write_serve_trace_summary)
         return
     if args.write_sq_summary:
         write_sq_summary(*args.write_sq_summary)
