@@ -1,6 +1,7 @@
 """CPU-side tests of the C ABI: the library loads and exports what the header
 declares, the float64 host fit matches the oracle's fit, and argument
 validation rejects bad calls before any device work."""
+import json
 import math
 import os
 import re
@@ -392,3 +393,24 @@ def test_fit_cache_save_load_roundtrip(tmp_path):
     with pytest.raises(F.FobfError):
         F.fit_cache_load(tmp_path / "missing.txt")
     assert F.fit_cache_clear() == 0
+
+
+def test_bench_traffic_tracks_the_kernel_sources(monkeypatch):
+    """bench.py reports the committed HBM-traffic counters only for the
+    kernel code they were taken from: a source hash other than the
+    recorded one (any code change in the kernels or their launch
+    configuration) turns the figure into null instead of a stale number."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    with open(os.path.join(ROOT, "profiles", "fobf_c3_hbm_traffic.json")) as fh:
+        rec = json.load(fh)
+    ent = rec["mfma_f32_ws_kernel_c3"]
+    got = bench.traffic_record("mfma_f32_ws_kernel_c3", None)
+    if ent["source_hash"] == bench.kernel_source_hash():
+        assert got == ent["bytes_per_launch"] > 0
+    else:
+        assert got is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.traffic_record("mfma_f32_ws_kernel_c3", None) is None
