@@ -31,7 +31,7 @@ __global__ __launch_bounds__(MTHREADS, (SH <= 20 ? 2 : 1)) void mfma_f32_kernel(
   __syncthreads();
   build_f32_tables<SH>(im, tbl, p.r, Bt, At);
   __syncthreads();
-  f32_tile<SH>(im, tx, ty, nblk, tbl, Bt, At, nd);
+  f32_tile<SH, true>(im, tx, ty, nblk, tbl, Bt, At, nd);
 }
 
 template <typename OT, int DV>

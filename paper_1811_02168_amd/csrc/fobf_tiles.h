@@ -262,7 +262,11 @@ __device__ __forceinline__ void poison_lds(const Img& im, int from_bytes = 0) {
 __device__ __forceinline__ int hrow_of_lane(int li) { return 4 * (li & 3) + (li >> 2); }
 
 // One channel group over this wave's strip: G = 1 is {f} (k = 0, no trig),
-// G = 4 is {C f, S f, C, S} of frequency k >= 1.  Bt / At are the
+// G = 4 is {C f, S f, C, S} of frequency k >= 1, G = 5 is f followed by
+// frequency k = 1's four channels (the f channel's single accumulator
+// chain then overlaps four others; its fold adds f's term and then
+// frequency 1's, the order of two separate passes, so the output is the
+// same bit for bit).  Bt / At are the
 // horizontal / vertical Toeplitz slices, one float per lane per MFMA step,
 // precomputed in LDS.
 //
@@ -337,7 +341,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
         // with pb < 0 fold nothing); the scheduling group keeps the loads
         // at the head of the block
         float fo[4];
-        if (G == 4) {
+        if (G >= 4) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int gy = min(max(y0 + 16 * pb + 4 * lk + v, 0), im.H - 1);
@@ -377,12 +381,14 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
           if (G == 1) {
             a[0] = f;
           } else {
+            constexpr int g0 = G == 5 ? 1 : 0;
             float sn, cs;
             sincos_rev(kinv * f, &sn, &cs);
-            a[0] = cs * f;
-            a[1] = sn * f;
-            a[2] = EDGE ? cs * m : cs;
-            a[3] = EDGE ? sn * m : sn;
+            if (G == 5) a[0] = f;
+            a[g0] = cs * f;
+            a[g0 + 1] = sn * f;
+            a[g0 + 2] = EDGE ? cs * m : cs;
+            a[g0 + 3] = EDGE ? sn * m : sn;
           }
 #pragma unroll
           for (int g = 0; g < G; ++g)
@@ -420,7 +426,7 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             nv[v] = nrow[64 * v];
-            if (G == 4) dv[v] = drow[64 * v];
+            if (G >= 4) dv[v] = drow[64 * v];
           }
           chk_nd(im, nrow, 193);
           chk_nd(im, drow, 193);
@@ -429,16 +435,18 @@ __device__ __forceinline__ void f32_group(const Img& im, int k, int x0w, int y0,
             if (G == 1) {
               nv[v] = fmaf(ck, vacc[0][v], nv[v]);
             } else {
+              constexpr int g0 = G == 5 ? 1 : 0;
+              if (G == 5) nv[v] = fmaf(cS[0], vacc[0][v], nv[v]);
               float sn, cs;
               sincos_rev(kinv * fo[v], &sn, &cs);
-              nv[v] = fmaf(ck, fmaf(cs, vacc[0][v], sn * vacc[1][v]), nv[v]);
-              dv[v] = fmaf(ck, fmaf(cs, vacc[2][v], sn * vacc[3][v]), dv[v]);
+              nv[v] = fmaf(ck, fmaf(cs, vacc[g0][v], sn * vacc[g0 + 1][v]), nv[v]);
+              dv[v] = fmaf(ck, fmaf(cs, vacc[g0 + 2][v], sn * vacc[g0 + 3][v]), dv[v]);
             }
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             nrow[64 * v] = nv[v];
-            if (G == 4) drow[64 * v] = dv[v];
+            if (G >= 4) drow[64 * v] = dv[v];
           }
         }
       }
@@ -532,7 +540,9 @@ __device__ __forceinline__ bool tile_of_block(int L, int nblocks, int ntx, int n
   return true;
 }
 
-template <int SH>
+// MERGE: f is taken with frequency 1 (G = 5, same output as separate
+// passes; the single-image kernel, whose registers have the room).
+template <int SH, bool MERGE = false>
 __device__ __forceinline__ void f32_tile(const Img& im, int tx, int ty, int nblk,
                                          const float* tbl, const float* Bt, const float* At,
                                          float* nd) {
@@ -543,13 +553,21 @@ __device__ __forceinline__ void f32_tile(const Img& im, int tx, int ty, int nblk
   const int x0w = tx * (MWAVES * MSTRIP) + wave * MSTRIP;
   const int y0 = ty * 16 * nblk;
   init_nd(im, tbl, x0w, y0, nblk, Ns, Ds, lane);
+  const bool merge = MERGE && im.K > 1;
+  const int k1 = merge ? 2 : 1;
   if (strip_interior<SH>(im, x0w, y0, nblk)) {
-    f32_group<SH, 1, false>(im, 0, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
-    for (int k = 1; k < im.K; ++k)
+    if (merge)
+      f32_group<SH, 5, false>(im, 1, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+    else
+      f32_group<SH, 1, false>(im, 0, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+    for (int k = k1; k < im.K; ++k)
       f32_group<SH, 4, false>(im, k, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
   } else {
-    f32_group<SH, 1, true>(im, 0, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
-    for (int k = 1; k < im.K; ++k)
+    if (merge)
+      f32_group<SH, 5, true>(im, 1, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+    else
+      f32_group<SH, 1, true>(im, 0, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
+    for (int k = k1; k < im.K; ++k)
       f32_group<SH, 4, true>(im, k, x0w, y0, nblk, tbl, Bt, At, Ns, Ds, lane);
   }
   store_nd(im, x0w, y0, nblk, Ns, Ds, lane);
