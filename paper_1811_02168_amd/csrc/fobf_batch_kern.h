@@ -96,7 +96,7 @@ __global__ __launch_bounds__(MTHREADS, batch_min_blocks<DVHI>()) void batch_kern
     if constexpr ((S + 3) / 4 >= DVLO && (S + 3) / 4 <= DVHI) {           \
       build_f32_tables<S>(im, tbl, im.r, Bt, At);                         \
       __syncthreads();                                                    \
-      f32_tile<S>(im, tx, ty, nblk, tbl, Bt, At, nd);                     \
+      f32_tile<S, true>(im, tx, ty, nblk, tbl, Bt, At, nd);               \
     }                                                                     \
     break;
 #define FOBF_F32_CASES(D) \

@@ -541,7 +541,7 @@ __device__ __forceinline__ bool tile_of_block(int L, int nblocks, int ntx, int n
 }
 
 // MERGE: f is taken with frequency 1 (G = 5, same output as separate
-// passes; the single-image kernel, whose registers have the room).
+// passes; the single-image and batch kernels take it at no register cost).
 template <int SH, bool MERGE = false>
 __device__ __forceinline__ void f32_tile(const Img& im, int tx, int ty, int nblk,
                                          const float* tbl, const float* Bt, const float* At,
