@@ -699,8 +699,17 @@ template <int G>
 constexpr int group_freqs() { return G / 4; }
 template <typename OT, bool GND>
 constexpr bool staged_merge() { return GND && Stage<OT>::kParts == 1; }
-template <typename OT, bool GND>
-constexpr int staged_channels() { return staged_merge<OT, GND>() ? 8 : STAGE_CH; }
+// The two-word workspace forms take f with frequency 1 (five channels) at
+// DV <= 4; their horizontal Toeplitz slices then live in the LDS, which
+// frees the registers the fifth channel's ring takes.  Same output bit for
+// bit; measured at 4096^2, K = 8: -2 to -4% at theta = 2.5, 5, 8, and +1.5%
+// at DV = 5 (theta = 10), where it is not used.
+template <typename OT, int DV, bool GND>
+constexpr bool staged_fmerge2() { return GND && Stage<OT>::kParts == 2 && DV <= 4; }
+template <typename OT, int DV, bool GND>
+constexpr int staged_channels() {
+  return staged_merge<OT, GND>() ? 8 : (staged_fmerge2<OT, DV, GND>() ? 5 : STAGE_CH);
+}
 
 // Staging items: IW consecutive columns of one row of a 16-row block, one
 // item per thread.  Only the CWn = 16 NW + 2r columns that meet non-zero
@@ -738,7 +747,7 @@ constexpr int staged_bufs() { return GND ? 2 : 1; }
 template <typename OT, int DV, int NW, bool GND = false>
 constexpr size_t staged_stage_bytes() {
   return sizeof(typename Stage<OT>::T) * staged_bufs<OT, NW, GND>() * Stage<OT>::kParts *
-         staged_channels<OT, GND>() * 16 * stage_pitch(stage_width<DV, NW>());
+         staged_channels<OT, DV, GND>() * 16 * stage_pitch(stage_width<DV, NW>());
 }
 
 template <typename OT, int NW>
@@ -750,8 +759,14 @@ constexpr size_t staged_vtap_bytes() {
 }
 
 template <typename OT, int DV, int NW, bool GND = false>
+constexpr size_t staged_htap_bytes() {
+  return staged_fmerge2<OT, DV, GND>() ? static_cast<size_t>((DV + 1) / 2) * 2 * 64 * 16 : 0;
+}
+
+template <typename OT, int DV, int NW, bool GND = false>
 constexpr size_t staged_buf_bytes() {
-  return staged_stage_bytes<OT, DV, NW, GND>() + staged_vtap_bytes<OT, DV, NW>();
+  return staged_stage_bytes<OT, DV, NW, GND>() + staged_vtap_bytes<OT, DV, NW>() +
+         staged_htap_bytes<OT, DV, NW, GND>();
 }
 
 // Issues the global loads of this thread's item of one block into
@@ -1128,13 +1143,13 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
   typedef typename S::T o4 __attribute__((ext_vector_type(4)));
   constexpr bool HF = group_has_f<G>();      // channel f leads the group
   constexpr int NF = group_freqs<G>();       // frequencies k .. k+NF-1
-  constexpr int SCH = staged_channels<OT, GND>();
+  constexpr int SCH = staged_channels<OT, DV, GND>();
   static_assert(G == (HF ? 1 : 0) + 4 * NF && G <= SCH, "bad channel group");
   // sub-groups: {f} when present, then one per frequency (4 channels)
   constexpr int NSG = (HF ? 1 : 0) + NF;
   // the merged groups run sub-group by sub-group (fewer accumulators live
   // at once); one-frequency groups keep their all-channels-at-once order
-  constexpr bool SUB = staged_merge<OT, GND>();
+  constexpr bool SUB = staged_merge<OT, GND>() || G == 5;
   auto sg_first = [](int sg) { return HF ? (sg == 0 ? 0 : 4 * sg - 3) : 4 * sg; };
   auto sg_size = [](int sg) { return (HF && sg == 0) ? 1 : 4; };
   constexpr int SHS = (DV + 1) / 2;          // 32-column horizontal steps
@@ -1171,6 +1186,21 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
       Bw[s][0][j] = S::cvt(w);
       if (NS == 2) Bw[s][NS - 1][j] = S::cvt(w - static_cast<float>(Bw[s][0][j]));
     }
+  // (two-word workspace forms with f merged: built by wave 0 into the LDS
+  // after the vertical slices and read back per horizontal step; every
+  // group writes the same values)
+  constexpr bool kHtapLds = staged_fmerge2<OT, DV, GND>();
+  v8* const htap = reinterpret_cast<v8*>(reinterpret_cast<char*>(sbuf) +
+                                         staged_stage_bytes<OT, DV, NW, GND>() +
+                                         staged_vtap_bytes<OT, DV, NW>());
+  if (kHtapLds && wave == 0)
+#pragma unroll
+    for (int s = 0; s < SHS; ++s)
+#pragma unroll
+      for (int h = 0; h < NS; ++h) {
+        chk_lds(im, htap + (s * NS + h) * 64 + lane, sizeof(v8));
+        htap[(s * NS + h) * 64 + lane] = Bw[s][h];
+      }
   // vertical weights: MFMA t pairs H blocks 2t (elements 0..3) and 2t+1
   // (elements 4..7); element j <-> H row 16 (2t + j/4) + 4 lk + j%4
   // (two-word modes: built by wave 0 into the LDS table after the staging
@@ -1346,7 +1376,9 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
             for (int ha = 0; ha < NS; ++ha)
 #pragma unroll
-              for (int hb = 0; hb + ha < NS; ++hb) acc[g] = S::mfma(a[ha], Bw[s][hb], acc[g]);
+              for (int hb = 0; hb + ha < NS; ++hb)
+                acc[g] = S::mfma(a[ha], kHtapLds ? htap[(s * NS + hb) * 64 + lane] : Bw[s][hb],
+                                 acc[g]);
           }
         // one buffer: every wave is done reading it before the next block
         // is staged into it
@@ -1460,7 +1492,9 @@ __device__ __forceinline__ void staged_group(const Img& im, int k, float shift, 
 #pragma unroll
               for (int ha = 0; ha < NS; ++ha)
 #pragma unroll
-                for (int hb = 0; hb + ha < NS; ++hb) acc[i] = S::mfma(a[ha], Bw[s][hb], acc[i]);
+                for (int hb = 0; hb + ha < NS; ++hb)
+                  acc[i] = S::mfma(a[ha], kHtapLds ? htap[(s * NS + hb) * 64 + lane] : Bw[s][hb],
+                                   acc[i]);
             }
 #pragma unroll
           for (int i = 0; i < gn; ++i)
@@ -1610,6 +1644,15 @@ __device__ __forceinline__ void staged_tile(const Img& im, int tx, int ty, int n
       for (; k + 1 < im.K; k += 2)
         staged_group<OT, DV, 8, NW, GND>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
       if (k < im.K)
+        staged_group<OT, DV, 4, NW, GND>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+    }
+  } else if constexpr (staged_fmerge2<OT, DV, GND>()) {
+    // {f, 1}, 2, 3, ..
+    if (im.K == 1) {
+      staged_group<OT, DV, 1, NW, GND>(im, 0, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+    } else {
+      staged_group<OT, DV, 5, NW, GND>(im, 1, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
+      for (int k = 2; k < im.K; ++k)
         staged_group<OT, DV, 4, NW, GND>(im, k, shift, x0, y0, nblk, tbl, sbuf, Ns, Ds);
     }
   } else {
